@@ -1,0 +1,193 @@
+/*
+ * mdp.h -- C ABI of the MI355X stochastic-flow MDP planner (libmdp.so).
+ *
+ * The planner implements the end-to-end method of Chowdhury & Subramani,
+ * "Optimal Path Planning of Autonomous Marine Vehicles in Stochastic Dynamic
+ * Ocean Flows using a GPU-Accelerated Algorithm":
+ *   mdp_build          -- Alg. 1 / Alg. 2: Monte-Carlo transition counts over
+ *                         flow realizations binned in a neighbouring sub-grid
+ *                         (Sec. III-B, III-C) and the expected one-step reward
+ *                         of each mission (Eqs. Rsa_time, Rsa_energyConsumption,
+ *                         Rsa_NetEnergy with the mean scalar field, Sec. III-A);
+ *   mdp_value_iterate  -- value iteration v_{k+1} = max_a sum P [r + v_k]
+ *                         (Sec. II-B, Sec. III-D);
+ *   mdp_policy         -- greedy policy pi = argmax_a sum P [r + v] (Sec. II-B).
+ *
+ * Conventions shared by every call
+ *   - Grid: nx * ny cells of size dx * dy, cell (i, j) = [i dx, (i+1) dx) x
+ *     [j dy, (j+1) dy); a state is (t, i, j) for decision layers t = 0..nt-1,
+ *     positioned at the cell centre (Sec. II-A).
+ *   - State index s = (t*ny + j)*nx + i, N_s = nt*nx*ny. Two absorbing sinks
+ *     follow the states: DEAD = N_s (obstacle, outside the domain, or beyond
+ *     the horizon) and TARGET = N_s + 1; both have value 0.
+ *   - Actions: a = jf*n_head + h with heading angle 2*pi*h/n_head
+ *     (counter-clockwise from east) and speed f_max*(jf+1)/n_speed.
+ *   - Row index of (s, a) is s*N_a + a, N_a = n_head*n_speed.
+ *   - Every device pointer is owned by the caller; the library never frees
+ *     caller memory and allocates no device memory inside these calls.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     null stream). Argument errors are returned synchronously; errors found
+ *     by the device are reported in the stats struct once the stream reaches
+ *     the end of the call.
+ *   - No call throws; every call returns an mdp_status.
+ *   - A context may be used by one host thread at a time. Calls that share a
+ *     scratch buffer must be ordered on one stream.
+ */
+#ifndef MDP_H
+#define MDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mdp_status;
+#define MDP_OK 0
+#define MDP_E_INVALID 1       /* bad argument, shape or pointer                    */
+#define MDP_E_CAPACITY 2      /* nnz_capacity too small; stats.nnz holds the need  */
+#define MDP_E_SUBGRID 3       /* a landing left the sub-grid; stats.n_escape > 0   */
+#define MDP_E_HIP 4           /* a HIP runtime call failed                          */
+#define MDP_E_NOT_CONVERGED 5 /* value iteration stopped at max_sweeps              */
+#define MDP_E_SCRATCH 6       /* scratch buffer smaller than mdp_build_query says   */
+
+#define MDP_MISSION_TIME 0       /* R = -dt                                      */
+#define MDP_MISSION_ENERGY 1     /* R = -c_f F^2 dt                              */
+#define MDP_MISSION_NET_ENERGY 2 /* R = E[-c_f F^2 + c_r (g(s) + g(s'))/2] dt    */
+
+#define MDP_FLAG_NEAR_EDGE 1u /* count samples within 1e-6 (physical) of an edge */
+
+#define MDP_MAX_ACTIONS 64
+#define MDP_MAX_MODES 16
+
+/* Problem statement: Alg. 1's prob_type, prob_params and grid_params. */
+typedef struct mdp_problem {
+  int32_t nx, ny, nt;        /* grid cells per axis and decision layers          */
+  int32_t n_modes, n_real;   /* K flow modes (<= 16), N_r realizations (<= 65535) */
+  int32_t n_head, n_speed;   /* headings and speeds, N_a = product <= 64          */
+  int32_t sub_hx, sub_hy;    /* sub-grid half widths; N_sg = (2hx+1)(2hy+1)       */
+  int32_t start_i, start_j;  /* start cell (reporting only)                       */
+  int32_t target_i, target_j;/* target cell                                       */
+  int32_t mean_time_varying; /* 0: ubar/vbar hold one layer, 1: nt layers         */
+  int32_t mode_time_varying; /* 0: phiu/phiv hold one layer, 1: nt layers         */
+  uint32_t mission_mask;     /* bit m set: build the reward of mission m          */
+  uint32_t flags;            /* MDP_FLAG_*                                        */
+  double dx, dy, dt, f_max;  /* cell sizes, time step, top agent speed            */
+  double r_term, r_outbound; /* arrival bonus, failure reward (Table I)           */
+  double c_f, c_r;           /* energy e(F) = c_f F^2; harvest coefficient c_r    */
+} mdp_problem;
+
+/* Reduced-order environment (Sec. II-C, Alg. 1 REQUIRE), device pointers,
+ * row-major, fp32 unless noted:
+ *   ubar, vbar  [Tm][ny][nx]     DO mean, Tm = nt if mean_time_varying else 1
+ *   phiu, phiv  [Tp][K][ny][nx]  DO modes, Tp = nt if mode_time_varying else 1
+ *   mu          [nt][K][n_real]  DO coefficients, realization index fastest
+ *   gbar        [nt+1][ny][nx]   mean scalar field; required for NET_ENERGY
+ *   mask        uint8 [nt+1][ny][nx]  obstacle mask (nonzero = blocked), or NULL */
+typedef struct mdp_env {
+  const float *ubar, *vbar;
+  const float *phiu, *phiv;
+  const float *mu;
+  const float *gbar;
+  const uint8_t *mask;
+} mdp_env;
+
+/* Sparse model in CSR, device pointers. Rows are ordered (t, j, i, a); the
+ * columns of a row are ascending (transient states of layer t+1, then DEAD,
+ * then TARGET); P(s'|s,a) = cnt / n_real.
+ *   row_ptr  int64  [N_s*N_a + 1]
+ *   col      int32  [nnz_capacity]
+ *   cnt      uint16 [nnz_capacity]    realizations landing in col
+ *   reward   fp32   [n_missions][N_s*N_a]  one block per set bit of
+ *                   mission_mask, in ascending mission order                */
+typedef struct mdp_model {
+  int64_t *row_ptr;
+  int32_t *col;
+  uint16_t *cnt;
+  float *reward;
+  int64_t nnz_capacity;
+} mdp_model;
+
+/* Sizes of a problem (host-only arithmetic, no device work). */
+typedef struct mdp_sizes {
+  int64_t n_states;        /* N_s                                              */
+  int64_t n_actions;       /* N_a                                              */
+  int64_t n_rows;          /* N_s * N_a                                        */
+  int64_t n_sg;            /* sub-grid cells                                   */
+  int64_t nnz_upper;       /* n_rows * min(N_sg, n_real): never exceeded        */
+  int64_t n_missions;      /* set bits of mission_mask                         */
+  int64_t scratch_bytes;   /* scratch needed by mdp_build / mdp_value_iterate  */
+  int64_t env_bytes;       /* bytes of the environment arrays                  */
+  int64_t layers_per_slab; /* decision layers handled per build pass           */
+} mdp_sizes;
+
+typedef struct mdp_build_stats {
+  int64_t samples;     /* (state, action, realization) landings computed       */
+  int64_t nnz;         /* nonzeros of the model (also when above capacity)     */
+  int64_t n_escape;    /* landings outside the sub-grid (must be 0)            */
+  int64_t n_near_edge; /* landings within 1e-6 of a cell edge; -1 if not asked */
+  int32_t status;      /* MDP_OK, MDP_E_CAPACITY or MDP_E_SUBGRID              */
+  int32_t n_slabs;     /* build passes                                         */
+} mdp_build_stats;
+
+typedef struct mdp_vi_stats {
+  int32_t sweeps;   /* synchronous sweeps run                                  */
+  int32_t status;   /* MDP_OK or MDP_E_NOT_CONVERGED                           */
+  double residual;  /* max_s |v_k(s) - v_{k-1}(s)| of the last sweep           */
+} mdp_vi_stats;
+
+typedef struct mdp_ctx mdp_ctx;
+
+/* Context bound to one HIP device. Holds no per-call state. */
+mdp_status mdp_ctx_create(int32_t device, mdp_ctx **out);
+mdp_status mdp_ctx_destroy(mdp_ctx *ctx);
+
+/* Static description of a status code. */
+const char *mdp_status_str(mdp_status s);
+
+/* Text of the last error recorded on this context ("" if none). */
+const char *mdp_last_error(const mdp_ctx *ctx);
+
+/* Sizes of every buffer a caller allocates for problem p (Alg. 1's
+ * allocations, done once by the caller instead of per (t, a)). */
+mdp_status mdp_build_query(const mdp_problem *p, mdp_sizes *out);
+
+/* Neighbouring sub-grid dimension (Alg. 1, "compute dimension"; Sec. III-B):
+ * the smallest hx, hy with h + 1/2 > (U + f_max) dt/d + 1e-3, U the largest
+ * |u| (|v|) over every synthesised velocity (t, cell, realization) in fp32.
+ * Runs on the device and waits for it (synchronous). p->sub_hx/hy are ignored. */
+mdp_status mdp_subgrid_auto(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env,
+                            int32_t *hx, int32_t *hy, void *stream);
+
+/* Build the sparse model (Alg. 1 with Alg. 2's per-sample work).
+ *   scratch      device buffer of at least mdp_sizes.scratch_bytes
+ *   stats        host memory written when the stream reaches the end of the
+ *                call (pinned memory keeps the call asynchronous)
+ * Landing cells are decided in fp32 with one fused multiply-add per mode term
+ * and per position update, so counts are reproducible bit for bit. */
+mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env,
+                     const mdp_model *model, void *scratch, size_t scratch_bytes,
+                     mdp_build_stats *stats, void *stream);
+
+/* Synchronous (Jacobi) value iteration on the model of mission `mission`
+ * (Sec. II-B update rule), from the values in d_v (v0; zeros for a cold start)
+ * until max_s |v_k - v_{k-1}| < tol or max_sweeps sweeps. Values are fp64,
+ * [N_s]; the result is left in d_v. Sums of each row are taken in a fixed
+ * order, so the layered model reaches a residual of exactly 0 after at most
+ * nt + 1 sweeps. */
+mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
+                             int32_t mission, double tol, int32_t max_sweeps, double *d_v,
+                             void *scratch, size_t scratch_bytes, mdp_vi_stats *stats,
+                             void *stream);
+
+/* Greedy policy (Sec. II-B): d_pi[s] = the lowest action index attaining
+ * max_a R(s,a) + sum_s' P(s'|s,a) v(s'), for every state. d_v fp64 [N_s],
+ * d_pi int32 [N_s]. */
+mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
+                      int32_t mission, const double *d_v, int32_t *d_pi, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDP_H */

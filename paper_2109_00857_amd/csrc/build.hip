@@ -1,0 +1,631 @@
+// Sparse-MDP build kernels for gfx950 (Alg. 1 and Alg. 2 of the paper,
+// redesigned): one workgroup owns a tile of cells at one decision layer and
+// all N_a actions of those cells, and walks the realizations in chunks.
+//
+//   phase A  (lane = realization): velocity synthesis u = ubar + sum_k mu_k phi_k
+//            and the cell-unit position px = fma(u, dt/dx, i + 1/2) once per
+//            (cell, realization), reused by every action. The coefficient
+//            loads mu[t][k][r] are contiguous across lanes.
+//   phase B  (lane = (cell, action) row): X = px + Hx[a], i' = floor(X), and a
+//            private LDS counter per sub-grid bin. Counters are laid out
+//            [bin][lane], so the 64 lanes of a wave always hit 64 distinct
+//            banks whatever bins they land in; with 16-bit counters two rows
+//            (lanes l and l + hw, hw = words per bin) share one word.
+//   compaction (lane = row): bins in ascending order become CSR columns of
+//            layer t+1 (out-of-domain, obstacle and beyond-horizon landings merge
+//            into DEAD, the target into TARGET), the expected reward of every
+//            mission is formed from the per-bin counts in fp64, and the entries
+//            are packed into the workgroup's staging block.
+// A one-block scan turns the per-workgroup entry counts into global offsets and
+// a copy kernel writes row_ptr / col / cnt.
+#include <math.h>
+
+#include "mdp_internal.h"
+
+namespace mdpk {
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x)
+{
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over the 256 threads of a workgroup. sh: 4 words of LDS.
+__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t *sh, uint32_t &total)
+{
+  const uint32_t inc = wave_incl_scan(x);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const uint32_t v = sh[w];
+    pre += (w < wave) ? v : 0u;
+    tot += v;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - x;
+}
+
+__device__ inline unsigned long long block_sum_u64(unsigned long long x, unsigned long long *sh)
+{
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[wave] = x;
+  __syncthreads();
+  unsigned long long tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) tot += sh[w];
+  __syncthreads();
+  return tot;
+}
+
+// floor(x) converted to int in one VALU op (exact for |x| < 2^31).
+__device__ inline int cvt_floor(float x)
+{
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// Atomic add to the 32-bit LDS word at byte address `addr`.
+__device__ inline void lds_add(int addr, uint32_t v)
+{
+  lds_u32 *p = (lds_u32 *)(uintptr_t)(uint32_t)addr;
+  (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// a * b + c on 24-bit signed operands in one VALU op.
+__device__ inline int mad_i24(int a, int b, int c)
+{
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+__device__ inline uint64_t pack_entry(int32_t col, uint32_t cnt)
+{
+  return (uint64_t)(uint32_t)col | ((uint64_t)cnt << 32);
+}
+
+template <int KMAX, bool PACK16, bool NEAR>
+__global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const SlabParams S)
+{
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int HW = P.hw;                              // words per bin (power of 2)
+  const int sstr = 2 * P.rch + 4;                   // floats per staged cell (padded)
+  uint32_t *hist = lds;
+  float *stage = reinterpret_cast<float *>(lds + P.nsg * HW);
+  float *tab = stage + P.cells_per_tile * sstr;     // Hx[kMaxA], Hy[kMaxA]
+  uint32_t *red = reinterpret_cast<uint32_t *>(tab + 2 * kMaxA);  // 16 words
+
+  const int tid = threadIdx.x;
+  const int wg = blockIdx.x;
+  const int tl = wg / P.tiles_per_layer;
+  const int tile = wg - tl * P.tiles_per_layer;
+  const int t = S.t0 + tl;
+  const int c0 = tile * P.cells_per_tile;
+  const int ncell = min(P.cells_per_tile, P.nc - c0);
+  const int nc = P.nc;
+
+  // ---- this lane's row (cell cl of the tile, action a)
+  const int cl = tid / P.na;
+  const int a = tid - cl * P.na;
+  const bool lane_row = tid < P.row_lanes && cl < ncell;
+  const int c = c0 + (lane_row ? cl : 0);
+  const int ci = c % P.nx, cj = c / P.nx;
+  const float hxa = P.tab[a];
+  const float hya = P.tab[kMaxA + a];
+  if (tid < P.na) {
+    tab[tid] = hxa;
+    tab[kMaxA + tid] = hya;
+  }
+  const bool is_target = (ci == P.ti && cj == P.tj);
+  const bool is_obst = P.mask != nullptr && P.mask[(size_t)t * nc + c] != 0;
+  const bool sampled = lane_row && !is_target && !is_obst;
+
+  for (int w = tid; w < P.nsg * HW; w += kBlock) hist[w] = 0u;
+
+  // word of bin (iy - cj + hy, ix - ci + hx) = (iy*W + ix)*HW + base
+  const int col_l = tid & (HW - 1);
+  const uint32_t inc = (PACK16 && (tid & HW)) ? 0x10000u : 1u;
+  // byte address in LDS of this lane's counter for bin (iy*W + ix) - offset:
+  // the dynamic allocation starts right after the kernel's static LDS
+  const int base4 = (int)__builtin_amdgcn_groupstaticsize() +
+                    (((P.hy - cj) * P.W + (P.hx - ci)) * HW + col_l) * 4;
+  const int HW4 = HW * 4;
+  const int W = P.W;
+
+  const int rmask = P.rch - 1;
+  const int rlane = tid & rmask;
+  const int qg = __builtin_amdgcn_readfirstlane(tid / P.rch);  // uniform per wave (rch >= 64)
+  const int nqg = kBlock / P.rch;
+  const size_t tm_off = (size_t)P.mean_tstride * t;
+  const size_t tp_off = (size_t)P.mode_tstride * t;
+  const float *mu_t = P.mu + (size_t)t * P.K * P.nr;
+
+  uint32_t near_cnt = 0, esc_cnt = 0;
+  __syncthreads();
+
+  for (int r0 = 0; r0 < P.nr; r0 += P.rch) {
+    const int nloc = min(P.rch, P.nr - r0);
+    // ---------------- phase A: lane = realization
+    {
+      const int r = r0 + rlane;
+      const bool rv = rlane < nloc;
+      float m[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) m[k] = (k < P.K && rv) ? mu_t[(size_t)k * P.nr + r] : 0.0f;
+      for (int q = qg; q < ncell; q += nqg) {
+        const int cq = c0 + q;
+        const int qi = cq % P.nx, qj = cq / P.nx;
+        const bool q_skip = (qi == P.ti && qj == P.tj) ||
+                            (P.mask != nullptr && P.mask[(size_t)t * nc + cq] != 0);
+        if (q_skip) continue;
+        float u = P.ubar[tm_off + cq];
+        float v = P.vbar[tm_off + cq];
+        const float *pu = P.phiu + tp_off + cq;
+        const float *pv = P.phiv + tp_off + cq;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < P.K) {
+            u = __builtin_fmaf(m[k], pu[(size_t)k * nc], u);
+            v = __builtin_fmaf(m[k], pv[(size_t)k * nc], v);
+          }
+        float px = __builtin_fmaf(u, P.lam_x, (float)qi + 0.5f);
+        float py = __builtin_fmaf(v, P.lam_y, (float)qj + 0.5f);
+        if (rv && !(fabsf(u) <= P.usafe && fabsf(v) <= P.vsafe)) {
+          // Possible escape: check every action exactly (a non-finite flow
+          // counts as escaping with every action).
+          uint32_t n = 0;
+          if (!isfinite(u) || !isfinite(v)) {
+            n = (uint32_t)P.na;
+          } else {
+            for (int aa = 0; aa < P.na; ++aa) {
+              const float X = px + tab[aa];
+              const float Y = py + tab[kMaxA + aa];
+              const int di = (int)floorf(X) - qi, dj = (int)floorf(Y) - qj;
+              n += (abs(di) > P.hx || abs(dj) > P.hy) ? 1u : 0u;
+            }
+          }
+          if (n) {  // the model is invalid anyway; keep the histogram in bounds
+            esc_cnt += n;
+            px = (float)qi + 0.5f;
+            py = (float)qj + 0.5f;
+          }
+        }
+        *reinterpret_cast<float2 *>(stage + q * sstr + 2 * rlane) = make_float2(px, py);
+      }
+    }
+    __syncthreads();
+    // ---------------- phase B: lane = (cell, action) row
+    if (sampled) {
+      // Staged positions of this row's cell are read 4 realizations at a time;
+      // the next group is loaded before the current group's counter updates.
+      const float4 *st4 = reinterpret_cast<const float4 *>(stage + cl * sstr);
+      const int n4 = nloc >> 2;
+      auto bin = [&](float px, float py) {
+        const float X = px + hxa;
+        const float Y = py + hya;
+        const int ix = cvt_floor(X);
+        const int iy = cvt_floor(Y);
+        lds_add(mad_i24(mad_i24(iy, W, ix), HW4, base4), inc);
+        if (NEAR)
+          near_cnt += ((fabsf(X - rintf(X)) < P.eps_x) || (fabsf(Y - rintf(Y)) < P.eps_y)) ? 1u : 0u;
+      };
+      // Two register sets alternate; a prefetch may read up to 16 bytes past
+      // this cell's padded block, which stays inside the LDS allocation (the
+      // next cell's block or the action table) and is never used.
+      int g = 0;
+      if (n4 > 0) {
+        float4 A0 = st4[0], A1 = st4[1];
+        for (; g + 2 <= n4; g += 2) {
+          const float4 B0 = st4[2 * g + 2], B1 = st4[2 * g + 3];
+          bin(A0.x, A0.y);
+          bin(A0.z, A0.w);
+          bin(A1.x, A1.y);
+          bin(A1.z, A1.w);
+          A0 = st4[2 * g + 4];
+          A1 = st4[2 * g + 5];
+          bin(B0.x, B0.y);
+          bin(B0.z, B0.w);
+          bin(B1.x, B1.y);
+          bin(B1.z, B1.w);
+        }
+        if (g < n4) {
+          bin(A0.x, A0.y);
+          bin(A0.z, A0.w);
+          bin(A1.x, A1.y);
+          bin(A1.z, A1.w);
+        }
+      }
+      const float2 *st2 = reinterpret_cast<const float2 *>(stage + cl * sstr);
+      for (int rr = n4 * 4; rr < nloc; ++rr) {
+        const float2 pp = st2[rr];
+        bin(pp.x, pp.y);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---------------- diagnostics
+  {
+    unsigned long long *red64 = reinterpret_cast<unsigned long long *>(red);
+    const unsigned long long e = block_sum_u64(esc_cnt, red64);
+    const unsigned long long nr_ = block_sum_u64(NEAR ? near_cnt : 0u, red64);
+    const unsigned long long smp = block_sum_u64(sampled ? (unsigned long long)P.nr : 0ull, red64);
+    if (tid == 0) {
+      if (e) atomicAdd(&S.st->n_escape, e);
+      if (nr_) atomicAdd(&S.st->n_near, nr_);
+      atomicAdd(&S.st->samples, smp);
+    }
+  }
+
+  // ---------------- compaction, pass 1: entries and rewards of the row
+  const int32_t ns = P.nt * nc;
+  const int32_t DEAD = ns, TARGET = ns + 1;
+  const size_t m1 = (size_t)(t + 1) * nc;
+  const bool last_layer = (t + 1 == P.nt);
+  const int jf = a / P.n_head;
+  const double F = P.f_max * (double)(jf + 1) / (double)P.n_speed;
+  const double e_a = P.c_f * F * F;
+  const double g_s = (P.gbar != nullptr && lane_row) ? (double)P.gbar[(size_t)t * nc + c] : 0.0;
+  const int shift = (PACK16 && (tid & HW)) ? 16 : 0;
+
+  uint32_t nnz = 0, dead = 0, tgt = 0, nstate = 0;
+  double gsum = 0.0;  // sum over state and target landings of count * gbar(s')
+  if (sampled) {
+    int b = 0;
+    for (int dj = -P.hy; dj <= P.hy; ++dj) {
+      const int jp = cj + dj;
+      for (int di = -P.hx; di <= P.hx; ++di, ++b) {
+        const uint32_t wv = hist[b * HW + col_l];
+        const uint32_t n = PACK16 ? ((wv >> shift) & 0xffffu) : wv;
+        if (n == 0) continue;
+        const int ip = ci + di;
+        if (ip < 0 || ip >= P.nx || jp < 0 || jp >= P.ny) {
+          dead += n;
+          continue;
+        }
+        const int cp = jp * P.nx + ip;
+        if (P.mask != nullptr && P.mask[m1 + cp] != 0) {
+          dead += n;
+        } else if (ip == P.ti && jp == P.tj) {
+          tgt += n;
+          if (P.gbar != nullptr) gsum += (double)n * (double)P.gbar[m1 + cp];
+        } else if (last_layer) {
+          dead += n;
+        } else {
+          ++nnz;
+          nstate += n;
+          if (P.gbar != nullptr) gsum += (double)n * (double)P.gbar[m1 + cp];
+        }
+      }
+    }
+    nnz += (dead ? 1u : 0u) + (tgt ? 1u : 0u);
+  } else if (lane_row) {
+    nnz = 1;
+  }
+
+  // ---------------- rewards (per-bin counts, fp64)
+  if (lane_row) {
+    const int64_t row = ((int64_t)t * nc + c) * P.na + a;
+    const double inv = 1.0 / (double)P.nr;
+    const double live = (double)(nstate + tgt);
+    const double fixed = P.r_term * (double)tgt + P.r_out * (double)dead;
+    for (int k = 0; k < P.nmiss; ++k) {
+      const int m = P.miss[k];
+      double Rm;
+      if (is_target) {
+        Rm = 0.0;
+      } else if (is_obst) {
+        Rm = P.r_out;
+      } else {
+        double s;
+        if (m == MDP_MISSION_TIME)
+          s = -P.dt * live + fixed;
+        else if (m == MDP_MISSION_ENERGY)
+          s = -e_a * P.dt * live + fixed;
+        else
+          s = (-e_a + 0.5 * P.c_r * g_s) * P.dt * live + 0.5 * P.c_r * P.dt * gsum + fixed;
+        Rm = s * inv;
+      }
+      P.reward[(int64_t)k * P.rows + row] = (float)Rm;
+    }
+  }
+
+  // ---------------- workgroup offsets
+  uint32_t total;
+  const uint32_t off = block_excl_scan(nnz, red, total);
+  const int64_t srow = (((int64_t)t * nc + c0) * P.na + tid) - S.row0;
+  if (lane_row) {
+    S.row_nnz[srow] = nnz;
+    S.row_off[srow] = off;
+  }
+  if (tid == 0) S.wg_nnz[wg] = total;
+
+  // ---------------- compaction, pass 2: write the row's entries
+  if (lane_row) {
+    uint64_t *out = S.stage + (int64_t)wg * S.wg_cap + off;
+    if (!sampled) {
+      out[0] = pack_entry(is_target ? TARGET : DEAD, (uint32_t)P.nr);
+    } else {
+      uint32_t k = 0;
+      int b = 0;
+      for (int dj = -P.hy; dj <= P.hy; ++dj) {
+        const int jp = cj + dj;
+        for (int di = -P.hx; di <= P.hx; ++di, ++b) {
+          const uint32_t wv = hist[b * HW + col_l];
+          const uint32_t n = PACK16 ? ((wv >> shift) & 0xffffu) : wv;
+          if (n == 0 || last_layer) continue;
+          const int ip = ci + di;
+          if (ip < 0 || ip >= P.nx || jp < 0 || jp >= P.ny) continue;
+          const int cp = jp * P.nx + ip;
+          if (P.mask != nullptr && P.mask[m1 + cp] != 0) continue;
+          if (ip == P.ti && jp == P.tj) continue;
+          out[k++] = pack_entry((int32_t)((t + 1) * nc + cp), n);
+        }
+      }
+      if (dead) out[k++] = pack_entry(DEAD, dead);
+      if (tgt) out[k++] = pack_entry(TARGET, tgt);
+    }
+  }
+}
+
+// Action displacement tables into device memory (one thread per entry).
+__global__ void k_fill_tab(const ActionTables T, float *tab)
+{
+  const int k = threadIdx.x;
+  float x = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxA; ++q)
+    if (q == k) x = (q < kMaxA) ? T.hx[q] : T.hy[q - kMaxA];
+  if (k < 2 * kMaxA) tab[k] = x;
+}
+
+__global__ void k_build_init(BuildState *st)
+{
+  if (threadIdx.x == 0) {
+    st->n_escape = 0;
+    st->n_near = 0;
+    st->samples = 0;
+    st->running_nnz = 0;
+  }
+}
+
+// Exclusive scan of the per-workgroup entry counts of one pass (one block).
+__global__ __launch_bounds__(1024) void k_scan_wg(const uint32_t *wg_nnz, int n, int64_t *wg_off,
+                                                  BuildState *st, int64_t *row_ptr_end)
+{
+  __shared__ long long sh[1024];
+  const int tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(n, tid * per), hi = min(n, lo + per);
+  long long s = 0;
+  for (int k = lo; k < hi; ++k) s += wg_nnz[k];
+  sh[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
+    long long y = (tid >= d) ? sh[tid - d] : 0;
+    __syncthreads();
+    sh[tid] += y;
+    __syncthreads();
+  }
+  const long long base = st->running_nnz;
+  long long acc = base + sh[tid] - s;
+  for (int k = lo; k < hi; ++k) {
+    wg_off[k] = acc;
+    acc += wg_nnz[k];
+  }
+  __syncthreads();
+  if (tid == 1023) {
+    const long long tot = base + sh[1023];
+    st->running_nnz = tot;
+    if (row_ptr_end) *row_ptr_end = tot;
+  }
+}
+
+// row_ptr of the pass's rows and the staged entries -> CSR (capacity-checked).
+__global__ __launch_bounds__(kBlock) void k_copy(const BuildParams P, const SlabParams S,
+                                                  const ModelOut M)
+{
+  const int tid = threadIdx.x;
+  const int wg = blockIdx.x;
+  const int tl = wg / P.tiles_per_layer;
+  const int tile = wg - tl * P.tiles_per_layer;
+  const int t = S.t0 + tl;
+  const int c0 = tile * P.cells_per_tile;
+  const int ncell = min(P.cells_per_tile, P.nc - c0);
+  const int64_t off = S.wg_off[wg];
+  if (tid < ncell * P.na) {
+    const int64_t row = ((int64_t)t * P.nc + c0) * P.na + tid;
+    M.row_ptr[row] = off + S.row_off[row - S.row0];
+  }
+  const uint32_t n = S.wg_nnz[wg];
+  const uint64_t *src = S.stage + (int64_t)wg * S.wg_cap;
+  for (uint32_t k = tid; k < n; k += kBlock) {
+    const int64_t d = off + k;
+    if (d < M.capacity) {
+      const uint64_t e = src[k];
+      M.col[d] = (int32_t)(uint32_t)e;
+      M.cnt[d] = (uint16_t)(e >> 32);
+    }
+  }
+}
+
+__global__ void k_build_finalize(BuildState *st, int64_t capacity, int n_slabs, int near_asked)
+{
+  if (threadIdx.x != 0) return;
+  mdp_build_stats o;
+  o.samples = (int64_t)st->samples;
+  o.nnz = st->running_nnz;
+  o.n_escape = (int64_t)st->n_escape;
+  o.n_near_edge = near_asked ? (int64_t)st->n_near : -1;
+  o.status = o.n_escape ? MDP_E_SUBGRID : (o.nnz > capacity ? MDP_E_CAPACITY : MDP_OK);
+  o.n_slabs = n_slabs;
+  st->out = o;
+}
+
+// Exact escape count without a histogram, for sub-grids too small to hold even
+// the agent's own displacement (the model is then not built).
+__global__ __launch_bounds__(kBlock) void k_escape_only(const BuildParams P, BuildState *st)
+{
+  const int nc = P.nc;
+  const int64_t total = (int64_t)P.nt * nc * P.nr;
+  unsigned long long n = 0, smp = 0;
+  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < total;
+       id += (int64_t)gridDim.x * kBlock) {
+    const int r = (int)(id % P.nr);
+    const int64_t tc = id / P.nr;
+    const int c = (int)(tc % nc);
+    const int t = (int)(tc / nc);
+    const int ci = c % P.nx, cj = c / P.nx;
+    if ((ci == P.ti && cj == P.tj) || (P.mask != nullptr && P.mask[(size_t)t * nc + c] != 0)) continue;
+    float u = P.ubar[(size_t)P.mean_tstride * t + c];
+    float v = P.vbar[(size_t)P.mean_tstride * t + c];
+    for (int k = 0; k < P.K; ++k) {
+      const float m = P.mu[((size_t)t * P.K + k) * P.nr + r];
+      u = __builtin_fmaf(m, P.phiu[(size_t)P.mode_tstride * t + (size_t)k * nc + c], u);
+      v = __builtin_fmaf(m, P.phiv[(size_t)P.mode_tstride * t + (size_t)k * nc + c], v);
+    }
+    const float px = __builtin_fmaf(u, P.lam_x, (float)ci + 0.5f);
+    const float py = __builtin_fmaf(v, P.lam_y, (float)cj + 0.5f);
+    for (int a = 0; a < P.na; ++a) {
+      const float X = px + P.tab[a], Y = py + P.tab[kMaxA + a];
+      const int di = (int)floorf(X) - ci, dj = (int)floorf(Y) - cj;
+      n += (abs(di) > P.hx || abs(dj) > P.hy) ? 1ull : 0ull;
+    }
+    smp += P.na;
+  }
+  __shared__ unsigned long long sh[4];
+  const unsigned long long tn = block_sum_u64(n, sh);
+  const unsigned long long ts = block_sum_u64(smp, sh);
+  if (threadIdx.x == 0) {
+    if (tn) atomicAdd(&st->n_escape, tn);
+    atomicAdd(&st->samples, ts);
+  }
+}
+
+// Largest |u| and |v| over all synthesised velocities (bits of non-negative
+// floats order like unsigned integers).
+__global__ __launch_bounds__(kBlock) void k_max_speed(const BuildParams P, unsigned int *bits)
+{
+  const int nc = P.nc;
+  const int64_t total = (int64_t)P.nt * nc * P.nr;
+  float mu_ = 0.0f, mv = 0.0f;
+  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < total;
+       id += (int64_t)gridDim.x * kBlock) {
+    const int r = (int)(id % P.nr);
+    const int64_t tc = id / P.nr;
+    const int c = (int)(tc % nc);
+    const int t = (int)(tc / nc);
+    float u = P.ubar[(size_t)P.mean_tstride * t + c];
+    float v = P.vbar[(size_t)P.mean_tstride * t + c];
+    for (int k = 0; k < P.K; ++k) {
+      const float m = P.mu[((size_t)t * P.K + k) * P.nr + r];
+      u = __builtin_fmaf(m, P.phiu[(size_t)P.mode_tstride * t + (size_t)k * nc + c], u);
+      v = __builtin_fmaf(m, P.phiv[(size_t)P.mode_tstride * t + (size_t)k * nc + c], v);
+    }
+    mu_ = fmaxf(mu_, fabsf(u));
+    mv = fmaxf(mv, fabsf(v));
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    mu_ = fmaxf(mu_, __shfl_xor(mu_, d, 64));
+    mv = fmaxf(mv, __shfl_xor(mv, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&bits[0], __float_as_uint(mu_));
+    atomicMax(&bits[1], __float_as_uint(mv));
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_fill_tab(const ActionTables &T, float *tab, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_fill_tab, dim3(1), dim3(2 * kMaxA), 0, s, T, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_init(BuildState *st, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+template <int KMAX, bool PACK16, bool NEAR>
+static hipError_t launch_build_t(const BuildParams &P, const SlabParams &S, size_t lds, hipStream_t s)
+{
+  auto kern = k_build<KMAX, PACK16, NEAR>;
+  static bool attr_set = false;  // raise the dynamic-LDS limit once per instantiation
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int n_wg = S.nlayers * P.tiles_per_layer;
+  hipLaunchKernelGGL(kern, dim3(n_wg), dim3(kBlock), lds, s, P, S);
+  return hipGetLastError();
+}
+
+template <int KMAX>
+static hipError_t launch_build_k(const BuildParams &P, const SlabParams &S, bool pack16, bool near,
+                                 size_t lds, hipStream_t s)
+{
+  if (pack16)
+    return near ? launch_build_t<KMAX, true, true>(P, S, lds, s) : launch_build_t<KMAX, true, false>(P, S, lds, s);
+  return near ? launch_build_t<KMAX, false, true>(P, S, lds, s) : launch_build_t<KMAX, false, false>(P, S, lds, s);
+}
+
+hipError_t launch_build_slab(const BuildParams &P, const SlabParams &S, int kmax, bool pack16, bool near,
+                             size_t lds, hipStream_t s)
+{
+  switch (kmax) {
+    case 4: return launch_build_k<4>(P, S, pack16, near, lds, s);
+    case 8: return launch_build_k<8>(P, S, pack16, near, lds, s);
+    default: return launch_build_k<16>(P, S, pack16, near, lds, s);
+  }
+}
+
+hipError_t launch_scan_wg(const SlabParams &S, int n_wg, int64_t *row_ptr_end, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_scan_wg, dim3(1), dim3(1024), 0, s, S.wg_nnz, n_wg, S.wg_off, S.st, row_ptr_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const BuildParams &P, const SlabParams &S, const ModelOut &M, int n_wg, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_copy, dim3(n_wg), dim3(kBlock), 0, s, P, S, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_finalize(BuildState *st, int64_t capacity, int n_slabs, int near_asked, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_build_finalize, dim3(1), dim3(64), 0, s, st, capacity, n_slabs, near_asked);
+  return hipGetLastError();
+}
+
+hipError_t launch_escape_only(const BuildParams &P, BuildState *st, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_escape_only, dim3(2048), dim3(kBlock), 0, s, P, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_speed(const BuildParams &P, unsigned int *bits, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_max_speed, dim3(2048), dim3(kBlock), 0, s, P, bits);
+  return hipGetLastError();
+}
+
+}  // namespace mdpk

@@ -1,0 +1,114 @@
+// Internal declarations shared by the planner's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mdp.h"
+
+namespace mdpk {
+
+constexpr int kBlock = 256;          // threads per workgroup of every build / VI kernel
+constexpr int kMaxA = MDP_MAX_ACTIONS;
+
+// Device-side bookkeeping at the start of the build scratch.
+struct BuildState {
+  unsigned long long n_escape;
+  unsigned long long n_near;
+  unsigned long long samples;
+  long long running_nnz;  // nonzeros of all slabs finished so far
+  mdp_build_stats out;    // filled by the finalize kernel, copied to the host
+  long long pad[8];
+};
+
+// Problem-wide parameters of the build kernels (passed by value).
+struct BuildParams {
+  const float *ubar, *vbar, *phiu, *phiv, *mu, *gbar;
+  const uint8_t *mask;
+  float *reward;            // [nmiss][rows]
+  int64_t rows;
+  int nx, ny, nt, nc, na, nr, K;
+  int hx, hy, W, nsg;
+  int ti, tj;               // target cell
+  int mean_tstride;         // nc if the mean varies in time, else 0 (elements)
+  int64_t mode_tstride;     // K*nc if the modes vary in time, else 0
+  int cells_per_tile, tiles_per_layer, rch;
+  int row_lanes;            // lanes that own a (cell, action) row: 256, 128 or 64
+  int hw;                   // LDS words per sub-grid bin (row_lanes, or half with 16-bit counters)
+  int nmiss, miss[3];
+  int n_head, n_speed;
+  float lam_x, lam_y, eps_x, eps_y;
+  float usafe, vsafe;       // |u| <= usafe and |v| <= vsafe rule out any escape
+  double dt, r_term, r_out, c_f, c_r, f_max;
+  const float *tab;         // device [2][kMaxA]: Hx then Hy (cell units per step)
+};
+
+// Host-side action tables, copied to the device by a one-thread-per-entry kernel.
+struct ActionTables {
+  float hx[kMaxA], hy[kMaxA];
+};
+
+// Per-pass parameters: one pass covers decision layers [t0, t0 + nlayers).
+struct SlabParams {
+  int t0, nlayers;
+  int64_t row0;             // first global row of the pass
+  uint32_t *row_nnz;        // [pass rows]
+  uint32_t *row_off;        // [pass rows] offset of the row inside its workgroup's block
+  uint32_t *wg_nnz;         // [pass workgroups]
+  int64_t *wg_off;          // [pass workgroups] global offset of the block
+  uint64_t *stage;          // [pass workgroups][wg_cap] packed (col, cnt)
+  int64_t wg_cap;
+  BuildState *st;
+};
+
+struct ModelOut {
+  int64_t *row_ptr;
+  int32_t *col;
+  uint16_t *cnt;
+  int64_t capacity;
+};
+
+// Launchers (return hipError_t of the launch)
+hipError_t launch_fill_tab(const ActionTables &T, float *tab, hipStream_t s);
+hipError_t launch_build_init(BuildState *st, hipStream_t s);
+hipError_t launch_build_slab(const BuildParams &P, const SlabParams &S, int kmax, bool pack16,
+                             bool near, size_t lds_bytes, hipStream_t s);
+hipError_t launch_scan_wg(const SlabParams &S, int n_wg, int64_t *row_ptr_end, hipStream_t s);
+hipError_t launch_copy(const BuildParams &P, const SlabParams &S, const ModelOut &M, int n_wg,
+                       hipStream_t s);
+hipError_t launch_build_finalize(BuildState *st, int64_t capacity, int n_slabs, int near_asked,
+                                 hipStream_t s);
+hipError_t launch_escape_only(const BuildParams &P, BuildState *st, hipStream_t s);
+hipError_t launch_max_speed(const BuildParams &P, unsigned int *umax_bits, hipStream_t s);
+
+// Value iteration / policy
+struct VIState {
+  unsigned long long res_bits;  // running max of |v_new - v_old| (bits of a non-negative double)
+  unsigned int wg_count;
+  int done;
+  int sweeps;
+  int status;
+  double last_res;
+  long long pad[4];
+};
+
+struct VIParams {
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const uint16_t *cnt;
+  const float *R;           // reward block of the mission
+  int64_t cap;              // length of col / cnt
+  int64_t ns;
+  int na, states_per_wg, n_wg;
+  double inv_nr, tol;
+  VIState *st;
+};
+
+hipError_t launch_vi_init(VIState *st, hipStream_t s);
+hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, int parity,
+                           hipStream_t s);
+hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, mdp_vi_stats *dev_stats,
+                            hipStream_t s);
+hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s);
+
+}  // namespace mdpk

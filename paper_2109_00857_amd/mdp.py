@@ -1,0 +1,285 @@
+"""Python binding of libmdp.so (include/mdp.h): argument marshalling only.
+
+Every computation runs in the HIP kernels behind the C ABI. PyTorch supplies
+device memory and streams. The functions named like the C entry points
+(``mdp_build``, ``mdp_value_iterate``, ``mdp_policy``, ...) pass their
+arguments straight through; ``Planner`` adds allocation conveniences on top.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmdp.so")
+
+MDP_OK = 0
+MDP_E_INVALID = 1
+MDP_E_CAPACITY = 2
+MDP_E_SUBGRID = 3
+MDP_E_HIP = 4
+MDP_E_NOT_CONVERGED = 5
+MDP_E_SCRATCH = 6
+MDP_FLAG_NEAR_EDGE = 1
+MISSION_TIME, MISSION_ENERGY, MISSION_NET_ENERGY = 0, 1, 2
+
+
+class MdpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class MdpProblem(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nt", C.c_int32),
+        ("n_modes", C.c_int32), ("n_real", C.c_int32),
+        ("n_head", C.c_int32), ("n_speed", C.c_int32),
+        ("sub_hx", C.c_int32), ("sub_hy", C.c_int32),
+        ("start_i", C.c_int32), ("start_j", C.c_int32),
+        ("target_i", C.c_int32), ("target_j", C.c_int32),
+        ("mean_time_varying", C.c_int32), ("mode_time_varying", C.c_int32),
+        ("mission_mask", C.c_uint32), ("flags", C.c_uint32),
+        ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double), ("f_max", C.c_double),
+        ("r_term", C.c_double), ("r_outbound", C.c_double), ("c_f", C.c_double), ("c_r", C.c_double),
+    ]
+
+
+class MdpEnv(C.Structure):
+    _fields_ = [("ubar", C.c_void_p), ("vbar", C.c_void_p), ("phiu", C.c_void_p),
+                ("phiv", C.c_void_p), ("mu", C.c_void_p), ("gbar", C.c_void_p), ("mask", C.c_void_p)]
+
+
+class MdpModel(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("cnt", C.c_void_p),
+                ("reward", C.c_void_p), ("nnz_capacity", C.c_int64)]
+
+
+class MdpSizes(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_states", "n_actions", "n_rows", "n_sg", "nnz_upper",
+                                          "n_missions", "scratch_bytes", "env_bytes", "layers_per_slab")]
+
+
+class MdpBuildStats(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("nnz", C.c_int64), ("n_escape", C.c_int64),
+                ("n_near_edge", C.c_int64), ("status", C.c_int32), ("n_slabs", C.c_int32)]
+
+
+class MdpViStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("residual", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmdp.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = C.CDLL(LIB_PATH)
+        vp, P = C.c_void_p, C.POINTER(MdpProblem)
+        sigs = {
+            "mdp_ctx_create": ([C.c_int32, C.POINTER(vp)], C.c_int32),
+            "mdp_ctx_destroy": ([vp], C.c_int32),
+            "mdp_status_str": ([C.c_int32], C.c_char_p),
+            "mdp_last_error": ([vp], C.c_char_p),
+            "mdp_build_query": ([P, C.POINTER(MdpSizes)], C.c_int32),
+            "mdp_subgrid_auto": ([vp, P, C.POINTER(MdpEnv), C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp],
+                                 C.c_int32),
+            "mdp_build": ([vp, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), vp, C.c_size_t, vp, vp], C.c_int32),
+            "mdp_value_iterate": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp,
+                                   C.c_size_t, vp, vp], C.c_int32),
+            "mdp_policy": ([vp, P, C.POINTER(MdpModel), C.c_int32, vp, vp, vp], C.c_int32),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_error", "mdp_build_query",
+            "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_policy"]
+
+
+def problem_struct(p: dict) -> MdpProblem:
+    return MdpProblem(**{k: p[k] for k, _ in MdpProblem._fields_})
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- C entry points
+def mdp_status_str(status: int) -> str:
+    return load().mdp_status_str(status).decode()
+
+
+def mdp_ctx_create(device: int = 0):
+    h = C.c_void_p()
+    rc = load().mdp_ctx_create(device, C.byref(h))
+    if rc != MDP_OK:
+        raise MdpError(rc, f"mdp_ctx_create: {mdp_status_str(rc)}")
+    return h
+
+
+def mdp_ctx_destroy(ctx) -> None:
+    load().mdp_ctx_destroy(ctx)
+
+
+def mdp_last_error(ctx) -> str:
+    return load().mdp_last_error(ctx).decode()
+
+
+def mdp_build_query(problem: dict) -> dict:
+    s = MdpSizes()
+    rc = load().mdp_build_query(C.byref(problem_struct(problem)), C.byref(s))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_build_query: invalid problem")
+    return {k: getattr(s, k) for k, _ in MdpSizes._fields_}
+
+
+def _check(ctx, rc, what):
+    if rc != MDP_OK:
+        raise MdpError(rc, f"{what}: {mdp_status_str(rc)}: {mdp_last_error(ctx)}")
+
+
+def mdp_subgrid_auto(ctx, problem: dict, env: dict, stream=None):
+    hx, hy = C.c_int32(), C.c_int32()
+    e = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
+    rc = load().mdp_subgrid_auto(ctx, C.byref(problem_struct(problem)), C.byref(e), C.byref(hx),
+                                 C.byref(hy), _stream_handle(stream))
+    _check(ctx, rc, "mdp_subgrid_auto")
+    return hx.value, hy.value
+
+
+def mdp_build(ctx, problem: dict, env: dict, model: dict, scratch: torch.Tensor, stats: torch.Tensor,
+              stream=None) -> None:
+    """Enqueue the build; `stats` is a (pinned) uint8 host tensor of sizeof(mdp_build_stats)."""
+    e = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    rc = load().mdp_build(ctx, C.byref(problem_struct(problem)), C.byref(e), C.byref(m), _ptr(scratch),
+                          scratch.numel(), stats.data_ptr(), _stream_handle(stream))
+    _check(ctx, rc, "mdp_build")
+
+
+def mdp_value_iterate(ctx, problem: dict, model: dict, mission: int, tol: float, max_sweeps: int,
+                      v: torch.Tensor, scratch: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    rc = load().mdp_value_iterate(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, tol, max_sweeps,
+                                  _ptr(v), _ptr(scratch), scratch.numel(), stats.data_ptr(),
+                                  _stream_handle(stream))
+    _check(ctx, rc, "mdp_value_iterate")
+
+
+def mdp_policy(ctx, problem: dict, model: dict, mission: int, v: torch.Tensor, pi: torch.Tensor,
+               stream=None) -> None:
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    rc = load().mdp_policy(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, _ptr(v), _ptr(pi),
+                           _stream_handle(stream))
+    _check(ctx, rc, "mdp_policy")
+
+
+def stats_buffer(cls) -> torch.Tensor:
+    return torch.zeros(C.sizeof(cls), dtype=torch.uint8, pin_memory=True)
+
+
+def read_stats(buf: torch.Tensor, cls) -> dict:
+    s = cls.from_buffer_copy(bytes(buf.numpy()))
+    return {k: getattr(s, k) for k, _ in cls._fields_}
+
+
+# ---------------------------------------------------------------- conveniences
+class Planner:
+    """A context on one device plus allocation helpers (all device memory from torch)."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        self.ctx = mdp_ctx_create(device)
+
+    def close(self):
+        if self.ctx is not None:
+            mdp_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload_env(self, w) -> dict:
+        d = self.device
+        env = {k: torch.from_numpy(np.ascontiguousarray(getattr(w, k))).to(d)
+               for k in ("ubar", "vbar", "phiu", "phiv", "mu")}
+        env["gbar"] = None if w.gbar is None else torch.from_numpy(w.gbar).to(d)
+        env["mask"] = None if w.mask is None else torch.from_numpy(w.mask).to(d)
+        return env
+
+    def alloc_model(self, problem: dict, capacity: int) -> dict:
+        sz = mdp_build_query(problem)
+        d = self.device
+        return dict(
+            row_ptr=torch.empty(sz["n_rows"] + 1, dtype=torch.int64, device=d),
+            col=torch.empty(max(capacity, 1), dtype=torch.int32, device=d),
+            cnt=torch.empty(max(capacity, 1), dtype=torch.uint16, device=d),
+            reward=torch.empty((sz["n_missions"], sz["n_rows"]), dtype=torch.float32, device=d),
+        )
+
+    def scratch(self, problem: dict) -> torch.Tensor:
+        sz = mdp_build_query(problem)
+        return torch.empty(sz["scratch_bytes"], dtype=torch.uint8, device=self.device)
+
+    def build(self, problem: dict, env: dict, capacity: int | None = None, scratch=None, stream=None):
+        """Build with a capacity guess; rebuild once with the exact nnz if it was too small.
+        Returns (model, stats). Synchronises the stream."""
+        sz = mdp_build_query(problem)
+        if capacity is None:
+            capacity = min(sz["nnz_upper"], 4 * sz["n_rows"] + 1024)
+        if scratch is None:
+            scratch = self.scratch(problem)
+        for _ in range(2):
+            model = self.alloc_model(problem, capacity)
+            st = stats_buffer(MdpBuildStats)
+            mdp_build(self.ctx, problem, env, model, scratch, st, stream)
+            (stream or torch.cuda.current_stream()).synchronize()
+            stats = read_stats(st, MdpBuildStats)
+            if stats["status"] != MDP_E_CAPACITY:
+                break
+            capacity = stats["nnz"]
+        if stats["status"] == MDP_OK:
+            model["col"] = model["col"][: stats["nnz"]]
+            model["cnt"] = model["cnt"][: stats["nnz"]]
+        return model, stats
+
+    def value_iterate(self, problem: dict, model: dict, mission: int, tol: float = 1e-6,
+                      max_sweeps: int = 100000, v0=None, scratch=None, stream=None):
+        ns = mdp_build_query(problem)["n_states"]
+        v = torch.zeros(ns, dtype=torch.float64, device=self.device) if v0 is None else v0.clone()
+        if scratch is None:
+            scratch = self.scratch(problem)
+        st = stats_buffer(MdpViStats)
+        mdp_value_iterate(self.ctx, problem, model, mission, tol, max_sweeps, v, scratch, st, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        return v, read_stats(st, MdpViStats)
+
+    def policy(self, problem: dict, model: dict, mission: int, v: torch.Tensor, stream=None):
+        ns = mdp_build_query(problem)["n_states"]
+        pi = torch.empty(ns, dtype=torch.int32, device=self.device)
+        mdp_policy(self.ctx, problem, model, mission, v, pi, stream)
+        return pi

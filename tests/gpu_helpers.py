@@ -1,0 +1,63 @@
+"""Shared checks for the GPU parity tests: the HIP path against the CPU oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+# Values and rewards agree within 1e-5 of the oracle's absolute-reward scale
+# (expected |reward| of the row for R; the value of |rewards| under the oracle's
+# policy for v).
+REL_TOL = 1e-5
+
+
+def model_to_host(model: dict, stats: dict) -> dict:
+    nnz = stats["nnz"]
+    return dict(
+        row_ptr=model["row_ptr"].cpu().numpy(),
+        col=model["col"][:nnz].cpu().numpy(),
+        cnt=model["cnt"][:nnz].cpu().numpy().astype(np.int32),
+        reward=model["reward"].cpu().numpy(),
+    )
+
+
+def assert_counts_equal(g: dict, o: dict) -> None:
+    """Transition counts bit-exact: row pointers, columns and counts."""
+    np.testing.assert_array_equal(g["row_ptr"], o["row_ptr"])
+    np.testing.assert_array_equal(g["col"], o["col"])
+    np.testing.assert_array_equal(g["cnt"], o["cnt"])
+
+
+def assert_rewards_close(g: dict, o: dict, missions: list[int]) -> float:
+    """|R_gpu - R_oracle| <= 1e-5 * E|r| per row (exactly equal when E|r| = 0)."""
+    worst = 0.0
+    for slot, m in enumerate(missions):
+        Rg = g["reward"][slot].astype(np.float64)
+        Ro = o["R"][m]
+        A = o["A"][m]
+        err = np.abs(Rg - Ro)
+        bad = err > REL_TOL * A
+        assert not bad.any(), (m, np.flatnonzero(bad)[:10], Rg[bad][:5], Ro[bad][:5], A[bad][:5])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(A > 0, err / A, 0.0)
+        worst = max(worst, float(r.max(initial=0.0)))
+    return worst
+
+
+def assert_values_close(v_gpu: np.ndarray, v_ora: np.ndarray, w_ora: np.ndarray) -> float:
+    err = np.abs(v_gpu - v_ora)
+    bad = err > REL_TOL * w_ora
+    assert not bad.any(), (np.flatnonzero(bad)[:10], v_gpu[bad][:5], v_ora[bad][:5], w_ora[bad][:5])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return float(np.where(w_ora > 0, err / w_ora, 0.0).max(initial=0.0))
+
+
+def assert_policy_optimal(ora, w, om: dict, mission: int, v_ora, w_ora, pi_gpu) -> float:
+    """The GPU's action attains the oracle's max Q within the value tolerance.
+    Returns the exact-match rate with the oracle's policy."""
+    ns = w.n_states
+    q = ora.q_values(w, om, mission, v_ora, np.arange(ns))
+    qmax = q.max(axis=1)
+    qg = q[np.arange(ns), pi_gpu]
+    bad = qg < qmax - REL_TOL * w_ora
+    assert not bad.any(), (np.flatnonzero(bad)[:10], qg[bad][:5], qmax[bad][:5])
+    _, pi_ora, _ = ora.backward(w, om, mission)
+    return float((pi_ora == pi_gpu).mean())

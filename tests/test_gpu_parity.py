@@ -1,0 +1,193 @@
+"""HIP path vs CPU oracle, through the C ABI (needs an MI355X)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2109_00857_amd import workloads as W
+
+from gpu_helpers import (assert_counts_equal, assert_policy_optimal, assert_rewards_close,
+                         assert_values_close, model_to_host)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def planner():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2109_00857_amd import mdp
+
+    pl = mdp.Planner(0)
+    yield pl
+    pl.close()
+
+
+def _build_both(planner, ora, w, near=True):
+    from paper_2109_00857_amd import mdp
+
+    p = dict(w.problem)
+    if near:
+        p["flags"] |= mdp.MDP_FLAG_NEAR_EDGE
+    env = planner.upload_env(w)
+    model, stats = planner.build(p, env)
+    om = ora.build_model(w)
+    return p, env, model, stats, om
+
+
+def _full_parity(planner, ora, w, label):
+    import torch
+
+    print(f"[parity] {label}: {w.problem['nx']}x{w.problem['ny']}x{w.problem['nt']} "
+          f"Nr={w.problem['n_real']} Na={w.n_actions}", flush=True)
+    p, env, model, stats, om = _build_both(planner, ora, w)
+    assert stats["status"] == 0, stats
+    assert stats["n_escape"] == om["n_escape"] == 0
+    assert stats["n_near_edge"] == om["n_near_edge"]
+    g = model_to_host(model, stats)
+    assert stats["nnz"] == om["nnz"]
+    nc = w.problem["nx"] * w.problem["ny"]
+    src = np.arange(w.n_states) % nc
+    skipped = (src == w.problem["target_j"] * w.problem["nx"] + w.problem["target_i"])
+    if w.mask is not None:
+        skipped |= w.mask[:-1].reshape(-1).astype(bool)
+    assert stats["samples"] == int((~skipped).sum()) * w.n_actions * w.problem["n_real"]
+    assert_counts_equal(g, om)
+    missions = w.missions()
+    assert_rewards_close(g, om, missions)
+    for m in missions:
+        v, vst = planner.value_iterate(p, model, m, tol=1e-6)
+        assert vst["status"] == 0 and vst["sweeps"] <= w.problem["nt"] + 1, vst
+        v = v.cpu().numpy()
+        v_ora, pi_ora, w_ora = ora.backward(w, om, m)
+        assert_values_close(v, v_ora, w_ora)
+        pi = planner.policy(p, model, m, torch.from_numpy(v).to(planner.device))
+        rate = assert_policy_optimal(ora, w, om, m, v_ora, w_ora, pi.cpu().numpy())
+        print(f"[parity] {label} mission {m}: sweeps={vst['sweeps']} policy match={rate:.4f}", flush=True)
+    return p, env, model, stats, om
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_worked_example(planner, ora, case):
+    with open(os.path.join(GOLDEN, "worked_example_uniform_flow.json")) as f:
+        g = json.load(f)
+    c = g["cases"][case]
+    s = g["setup"]
+    w = W.uniform_flow(s["nx"], s["ny"], c["nt"], s["u0"], s["v0"], n_real=8, n_head=s["n_head"],
+                       f_max=s["f_max"], dx=s["dx"], dy=s["dy"], dt=s["dt"], start=tuple(s["start"]),
+                       target=tuple(s["target"]), sub_h=2)
+    p, env, model, stats, om = _full_parity(planner, ora, w, f"worked example T={c['nt']}")
+    v, _ = planner.value_iterate(p, model, 0)
+    pi = planner.policy(p, model, 0, v).cpu().numpy()
+    v = v.cpu().numpy()
+    nx, ny = s["nx"], s["ny"]
+    for st in c["states"]:
+        k = (st["t"] * ny + st["j"]) * nx + st["i"]
+        assert v[k] == st["v"] and pi[k] == st["pi"], st
+
+
+def test_c1_full(planner, ora):
+    """Config 1 as specified, sub-grid sized on the device and checked against the oracle."""
+    from paper_2109_00857_amd import mdp
+
+    w = W.config1()
+    env = planner.upload_env(w)
+    hx, hy = mdp.mdp_subgrid_auto(planner.ctx, w.problem, env)
+    assert (hx, hy) == ora.subgrid_auto(w)
+    w.problem["sub_hx"], w.problem["sub_hy"] = hx, hy
+    _full_parity(planner, ora, w, f"c1 (h={hx},{hy})")
+
+
+def test_c2_shape_ragged(planner, ora):
+    """Config-2 shapes (16 headings, 10 trig modes, AR(1), discs, all missions) on a
+    ragged grid and realization count that span many tiles and chunks."""
+    w = W.config2(nx=37, ny=29, nt=4, n_real=1000)
+    _full_parity(planner, ora, w, "c2-shaped ragged")
+
+
+def test_c3_shape_ragged(planner, ora):
+    """Config-3 shapes (32 headings, 16 modes, 7x7 sub-grid, net energy), ragged."""
+    w = W.config3(nx=23, ny=19, nt=3, n_real=700)
+    _full_parity(planner, ora, w, "c3-shaped ragged")
+
+
+def test_time_varying_fields_and_speeds(planner, ora):
+    """Time-varying mean and modes, two speeds, few modes (other kernel variants)."""
+    w = W.config2(nx=21, ny=18, nt=3, n_real=300, K=3, n_head=6)
+    rng = np.random.default_rng(3)
+    nt = w.problem["nt"]
+    w.ubar = np.ascontiguousarray(np.repeat(w.ubar, nt, 0) * rng.uniform(0.5, 1.5, (nt, 1, 1)).astype(np.float32))
+    w.vbar = np.ascontiguousarray(rng.normal(0, 0.05, w.ubar.shape).astype(np.float32))
+    w.phiu = np.ascontiguousarray(np.repeat(w.phiu, nt, 0) * rng.uniform(0.8, 1.2, (nt, 1, 1, 1)).astype(np.float32))
+    w.phiv = np.ascontiguousarray(np.repeat(w.phiv, nt, 0))
+    w.problem.update(mean_time_varying=1, mode_time_varying=1, n_speed=2, sub_hx=3, sub_hy=3)
+    w.problem["f_max"] = 0.25
+    w.check()
+    _full_parity(planner, ora, w, "time-varying, 2 speeds")
+
+
+def test_gaussian_bins_bitexact(planner, ora):
+    """The closed-form stochastic uniform-flow instance with 50000 realizations."""
+    w = W.uniform_flow(7, 7, 2, 0.25, 0.0, n_real=50000, n_head=4, f_max=0.6, sigma=0.2,
+                       start=(0, 0), target=(6, 6), sub_h=3, seed=11)
+    _full_parity(planner, ora, w, "gaussian bins")
+
+
+@pytest.mark.parametrize("h", [0, 1])
+def test_escape_detection(planner, ora, h):
+    """Too small a sub-grid: MDP_E_SUBGRID with the oracle's exact escape count."""
+    from paper_2109_00857_amd import mdp
+
+    w = W.config1(nt=3, n_real=200, sub_h=h)
+    p, env, model, stats, om = _build_both(planner, ora, w)
+    assert om["n_escape"] > 0
+    assert stats["status"] == mdp.MDP_E_SUBGRID
+    assert stats["n_escape"] == om["n_escape"]
+
+
+def test_capacity_too_small(planner, ora):
+    from paper_2109_00857_amd import mdp
+
+    w = W.config1(nt=3, n_real=100, sub_h=3)
+    env = planner.upload_env(w)
+    model = planner.alloc_model(w.problem, 1000)
+    scratch = planner.scratch(w.problem)
+    st = mdp.stats_buffer(mdp.MdpBuildStats)
+    mdp.mdp_build(planner.ctx, w.problem, env, model, scratch, st)
+    import torch
+
+    torch.cuda.synchronize()
+    s = mdp.read_stats(st, mdp.MdpBuildStats)
+    om = ora.build_model(w)
+    assert s["status"] == mdp.MDP_E_CAPACITY and s["nnz"] == om["nnz"] > 1000
+    np.testing.assert_array_equal(model["row_ptr"].cpu().numpy(), om["row_ptr"])
+
+
+def test_repeatable_bitwise(planner, ora):
+    w = W.config2(nx=30, ny=30, nt=3, n_real=500)
+    env = planner.upload_env(w)
+    m1, s1 = planner.build(w.problem, env)
+    m2, s2 = planner.build(w.problem, env)
+    assert s1 == s2
+    for k in ("row_ptr", "col", "cnt", "reward"):
+        assert (m1[k].view(-1).cpu().numpy().tobytes() == m2[k].view(-1).cpu().numpy().tobytes()), k
+    v1, _ = planner.value_iterate(w.problem, m1, 0)
+    v2, _ = planner.value_iterate(w.problem, m2, 0)
+    assert v1.cpu().numpy().tobytes() == v2.cpu().numpy().tobytes()
+
+
+def test_vi_layered_residual(planner, ora):
+    """Jacobi from v0 = 0 reaches residual exactly 0 within nt + 1 sweeps; with
+    tol = 0 it runs exactly max_sweeps and the values do not move."""
+    w = W.config1(nt=6, n_real=100, sub_h=3)
+    env = planner.upload_env(w)
+    model, stats = planner.build(w.problem, env)
+    v, st = planner.value_iterate(w.problem, model, 0, tol=1e-300)
+    assert st["status"] == 0 and st["residual"] == 0.0 and st["sweeps"] <= 7
+    v2, st2 = planner.value_iterate(w.problem, model, 0, tol=0.0, max_sweeps=9)
+    assert st2["sweeps"] == 9 and st2["status"] != 0
+    assert v.cpu().numpy().tobytes() == v2.cpu().numpy().tobytes()
