@@ -187,6 +187,18 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
 mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
                       int32_t mission, const double *d_v, int32_t *d_pi, void *stream);
 
+/* Per-kernel timing. While enabled, HIP events are recorded on the caller's
+ * stream around every launch of the kernels below; mdp_ctx_profile_read waits
+ * for the recorded events and returns the launch count and summed duration.
+ * Enabling (enable = 1) clears earlier records; disabling keeps them. */
+#define MDP_KERNEL_BUILD 0    /* histogram + compaction pass of mdp_build  */
+#define MDP_KERNEL_VI_SWEEP 1 /* one synchronous sweep of mdp_value_iterate */
+#define MDP_KERNEL_POLICY 2   /* mdp_policy                                 */
+#define MDP_KERNEL_COPY 3     /* staging-to-CSR copy of mdp_build           */
+#define MDP_N_KERNELS 4
+mdp_status mdp_ctx_profile(mdp_ctx *ctx, int32_t enable);
+mdp_status mdp_ctx_profile_read(mdp_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "mdp_internal.h"
 
@@ -17,12 +19,16 @@ struct mdp_ctx {
   int device;
   unsigned int *d_small;  // 256 bytes of device memory for synchronous helpers
   char err[512];
+  // per-kernel timing (only while profiling is enabled)
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MDP_N_KERNELS];
+  size_t ev_used[MDP_N_KERNELS] = {};
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kStageBudget = size_t(1) << 30;  // staging bytes per build pass
+constexpr size_t kStageBudget = size_t(4) << 30;  // staging bytes per build pass
 constexpr size_t kLdsLimit = 160 * 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -229,6 +235,35 @@ void fill_params(const mdp_problem *p, const mdp_env *env, const mdp_model *mode
   P.vsafe = safe_speed(p->sub_hy, my, p->dt / p->dy, p->ny);
 }
 
+// Events bracketing one launch of kernel kind k (no-ops unless profiling).
+struct Timed {
+  mdp_ctx *ctx;
+  int k;
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  Timed(mdp_ctx *c, int kind, hipStream_t st) : ctx(c), k(kind), s(st)
+  {
+    if (!ctx || !ctx->profiling) return;
+    auto &v = ctx->ev[k];
+    if (ctx->ev_used[k] == v.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      v.emplace_back(a, b);
+    }
+    auto &pr = v[ctx->ev_used[k]++];
+    (void)hipEventRecord(pr.first, s);
+    stop = pr.second;
+  }
+  ~Timed()
+  {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
 mdp_status hip_fail(mdp_ctx *ctx, hipError_t e, const char *where)
 {
   set_err(ctx, "%s: %s", where, hipGetErrorString(e));
@@ -279,11 +314,42 @@ mdp_status mdp_ctx_destroy(mdp_ctx *ctx)
 {
   if (!ctx) return MDP_E_INVALID;
   if (ctx->d_small) (void)hipFree(ctx->d_small);
+  for (auto &v : ctx->ev)
+    for (auto &pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   delete ctx;
   return MDP_OK;
 }
 
 const char *mdp_last_error(const mdp_ctx *ctx) { return ctx ? ctx->err : ""; }
+
+mdp_status mdp_ctx_profile(mdp_ctx *ctx, int32_t enable)
+{
+  if (!ctx) return MDP_E_INVALID;
+  if (enable)
+    for (size_t &u : ctx->ev_used) u = 0;
+  ctx->profiling = enable != 0;
+  return MDP_OK;
+}
+
+mdp_status mdp_ctx_profile_read(mdp_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms)
+{
+  if (!ctx || kernel < 0 || kernel >= MDP_N_KERNELS || !launches || !total_ms) return MDP_E_INVALID;
+  double tot = 0.0;
+  for (size_t i = 0; i < ctx->ev_used[kernel]; ++i) {
+    auto &pr = ctx->ev[kernel][i];
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(ctx, e, "event sync");
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, pr.first, pr.second)) != hipSuccess) return hip_fail(ctx, e, "elapsed");
+    tot += ms;
+  }
+  *launches = (int64_t)ctx->ev_used[kernel];
+  *total_ms = tot;
+  return MDP_OK;
+}
 
 mdp_status mdp_build_query(const mdp_problem *p, mdp_sizes *out)
 {
@@ -421,12 +487,18 @@ mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, con
       S.wg_cap = pl.wg_cap;
       S.st = st;
       const int n_wg = S.nlayers * pl.tiles_per_layer;
-      if ((e = launch_build_slab(P, S, pl.kmax, pl.pack16, near, pl.lds, s)) != hipSuccess)
-        return hip_fail(ctx, e, "build");
+      {
+        Timed tm(ctx, MDP_KERNEL_BUILD, s);
+        if ((e = launch_build_slab(P, S, pl.kmax, pl.pack16, near, pl.lds, s)) != hipSuccess)
+          return hip_fail(ctx, e, "build");
+      }
       const bool last = t0 + S.nlayers >= p->nt;
       if ((e = launch_scan_wg(S, n_wg, last ? model->row_ptr + pl.rows : nullptr, s)) != hipSuccess)
         return hip_fail(ctx, e, "scan");
-      if ((e = launch_copy(P, S, M, n_wg, s)) != hipSuccess) return hip_fail(ctx, e, "copy");
+      {
+        Timed tm(ctx, MDP_KERNEL_COPY, s);
+        if ((e = launch_copy(P, S, M, n_wg, s)) != hipSuccess) return hip_fail(ctx, e, "copy");
+      }
     }
   }
   if ((e = launch_build_finalize(st, model->nnz_capacity, n_slabs, near ? 1 : 0, s)) != hipSuccess)
@@ -464,7 +536,8 @@ static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *
   V.ns = (int64_t)p->nt * pl.nc;
   V.na = pl.na;
   V.states_per_wg = kBlock / pl.na;
-  V.n_wg = (int)((V.ns + V.states_per_wg - 1) / V.states_per_wg);
+  V.n_blocks = (V.ns + V.states_per_wg - 1) / V.states_per_wg;
+  V.n_wg = (int)std::min<int64_t>(V.n_blocks, 2048);
   V.inv_nr = 1.0 / (double)p->n_real;
   return MDP_OK;
 }
@@ -500,6 +573,7 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   for (int k = 0; k < n; ++k) {
     const double *vin = (k & 1) ? v_alt : d_v;
     double *vout = (k & 1) ? d_v : v_alt;
+    Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
     if ((e = launch_vi_sweep(V, vin, vout, k & 1, s)) != hipSuccess) return hip_fail(ctx, e, "vi sweep");
   }
   if ((e = launch_vi_finish(V, d_v, v_alt, dstats, s)) != hipSuccess) return hip_fail(ctx, e, "vi finish");
@@ -519,6 +593,7 @@ mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model
     set_err(ctx, "d_v and d_pi must be device pointers");
     return MDP_E_INVALID;
   }
+  Timed tm(ctx, MDP_KERNEL_POLICY, (hipStream_t)stream);
   hipError_t e = launch_policy(V, d_v, d_pi, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "policy");
   return MDP_OK;

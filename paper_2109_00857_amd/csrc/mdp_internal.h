@@ -99,7 +99,8 @@ struct VIParams {
   const float *R;           // reward block of the mission
   int64_t cap;              // length of col / cnt
   int64_t ns;
-  int na, states_per_wg, n_wg;
+  int na, states_per_wg, n_wg;   // n_wg: launched workgroups (grid-stride)
+  int64_t n_blocks;              // blocks of states_per_wg states
   double inv_nr, tol;
   VIState *st;
 };

@@ -1,10 +1,9 @@
 // Value iteration and greedy policy on the CSR model (Sec. II-B update rule).
 //
-// One thread per (state, action) row computes
+// A workgroup takes blocks of whole states (their N_a rows are contiguous) and
+// computes
 //     Q(s, a) = R(s, a) + (sum_k cnt_k * v_old[col_k]) / N_r      (fp64)
-// with the sinks DEAD and TARGET contributing 0; the N_a rows of a state are
-// contiguous, so a workgroup covers whole states and reduces max_a through
-// LDS. The sweep's residual max_s |v_new - v_old| is reduced on the device:
+// with the sinks DEAD and TARGET contributing 0, then max_a through LDS. The sweep's residual max_s |v_new - v_old| is reduced on the device:
 // every workgroup folds its maximum into one word with an atomic max, and the
 // last workgroup to finish records the sweep, decides convergence and resets
 // the accumulators for the next sweep. Later sweeps of the same call see the
@@ -13,39 +12,88 @@
 
 namespace mdpk {
 
-__device__ inline double row_q(const VIParams &P, const double *v, int64_t row)
+// Block b of the sweep as seen from this workgroup: workgroups are dealt to
+// the 8 XCDs round-robin, so each XCD is given a contiguous range of state
+// blocks and its L2 sees the neighbouring values those blocks gather.
+__device__ inline int64_t xcd_block(int64_t j, int64_t n_blocks, int &ok)
 {
-  // clamped to the column arrays, so a model whose build failed cannot send
-  // the sweep out of bounds
-  const int64_t lo = P.row_ptr[row], hi = min(P.row_ptr[row + 1], P.cap);
-  double acc = 0.0;
-  for (int64_t k = lo; k < hi; ++k) {
-    const uint32_t cidx = (uint32_t)P.col[k];
-    const double vv = (cidx < (uint32_t)P.ns) ? v[cidx] : 0.0;
-    acc += (double)P.cnt[k] * vv;
+  const int g = gridDim.x;
+  if ((g & 7) != 0) {
+    const int64_t blk = (int64_t)blockIdx.x + j * g;
+    ok = blk < n_blocks;
+    return blk;
   }
-  return (double)P.R[row] + acc * P.inv_nr;
+  const int64_t per_xcd = (n_blocks + 7) / 8;
+  const int64_t l = (int64_t)(blockIdx.x >> 3) + j * (g >> 3);
+  const int64_t blk = (int64_t)(blockIdx.x & 7) * per_xcd + l;
+  ok = (l < per_xcd) && (blk < n_blocks);
+  return blk;
 }
 
+constexpr int kChunk = 2048;  // entries staged in LDS per pass
+
+// Q(s, a) for the states of one block into q[]: the block's entries are
+// contiguous, so they are streamed with coalesced loads (col, cnt and the
+// gathered value) into LDS as products, then each row's thread adds its own
+// products in ascending entry order (the same order for every sweep).
+__device__ inline void block_q(const VIParams &P, const double *v, int64_t s0, int nst, int64_t *rp,
+                               double *prod, double *q)
+{
+  const int tid = threadIdx.x;
+  const int nrows = nst * P.na;
+  const int64_t row0 = s0 * P.na;
+  // nrows + 1 pointers (up to kBlock + 1): more entries than threads
+  for (int k = tid; k <= nrows; k += kBlock) rp[k] = min(max(P.row_ptr[row0 + k], (int64_t)0), P.cap);
+  __syncthreads();
+  const int64_t e0 = rp[0], e1 = rp[nrows];
+  const int64_t my_lo = (tid < nrows) ? rp[tid] : 0, my_hi = (tid < nrows) ? rp[tid + 1] : 0;
+  double acc = 0.0;
+  for (int64_t c0 = e0; c0 < e1; c0 += kChunk) {
+    const int n = (int)min((int64_t)kChunk, e1 - c0);
+    for (int k = tid; k < n; k += kBlock) {
+      const uint32_t cidx = (uint32_t)P.col[c0 + k];
+      const double vv = (cidx < (uint32_t)P.ns) ? v[cidx] : 0.0;
+      prod[k] = (double)P.cnt[c0 + k] * vv;
+    }
+    __syncthreads();
+    if (tid < nrows) {
+      const int64_t lo = max(my_lo, c0), hi = min(my_hi, c0 + n);
+      for (int64_t k = lo; k < hi; ++k) acc += prod[k - c0];
+    }
+    __syncthreads();
+  }
+  if (tid < nrows) q[tid] = (double)P.R[row0 + tid] + acc * P.inv_nr;
+  __syncthreads();
+}
+
+// One synchronous sweep over a chip-filling grid: one residual atomic per
+// workgroup, the last workgroup to finish closes the sweep.
 __global__ __launch_bounds__(kBlock) void k_vi_sweep(const VIParams P, const double *vin, double *vout,
                                                       int parity)
 {
+  __shared__ int64_t rp[kBlock + 1];
+  __shared__ double prod[kChunk];
   __shared__ double q[kBlock];
   __shared__ double wmax[kBlock / 64];
   if (P.st->done) return;
   const int tid = threadIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.x * P.states_per_wg;
-  const int nst = (int)min((int64_t)P.states_per_wg, P.ns - s0);
-  if (tid < nst * P.na) q[tid] = row_q(P, vin, s0 * P.na + tid);
-  __syncthreads();
   double d = 0.0;
-  if (tid < nst) {
-    const double *qs = q + tid * P.na;
-    double best = qs[0];
-    for (int a = 1; a < P.na; ++a) best = fmax(best, qs[a]);
-    const int64_t s = s0 + tid;
-    vout[s] = best;
-    d = fabs(best - vin[s]);
+  for (int64_t j = 0;; ++j) {
+    int ok;
+    const int64_t blk = xcd_block(j, P.n_blocks, ok);
+    if (!ok) break;
+    const int64_t s0 = blk * P.states_per_wg;
+    const int nst = (int)min((int64_t)P.states_per_wg, P.ns - s0);
+    block_q(P, vin, s0, nst, rp, prod, q);
+    if (tid < nst) {
+      const double *qs = q + tid * P.na;
+      double best = qs[0];
+      for (int a = 1; a < P.na; ++a) best = fmax(best, qs[a]);
+      const int64_t s = s0 + tid;
+      vout[s] = best;
+      d = fmax(d, fabs(best - vin[s]));
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
@@ -57,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep(const VIParams P, const dou
     atomicMax(&P.st->res_bits, (unsigned long long)__double_as_longlong(m));
     __threadfence();
     const unsigned int prev = atomicAdd(&P.st->wg_count, 1u);
-    if (prev == (unsigned int)P.n_wg - 1u) {
+    if (prev == gridDim.x - 1u) {
       __threadfence();
       const unsigned long long rb = atomicAdd(&P.st->res_bits, 0ull);
       const double res = __longlong_as_double((long long)rb);
@@ -103,22 +151,29 @@ __global__ __launch_bounds__(kBlock) void k_vi_finish(const VIParams P, double *
 
 __global__ __launch_bounds__(kBlock) void k_policy(const VIParams P, const double *v, int32_t *pi)
 {
+  __shared__ int64_t rp[kBlock + 1];
+  __shared__ double prod[kChunk];
   __shared__ double q[kBlock];
   const int tid = threadIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.x * P.states_per_wg;
-  const int nst = (int)min((int64_t)P.states_per_wg, P.ns - s0);
-  if (tid < nst * P.na) q[tid] = row_q(P, v, s0 * P.na + tid);
-  __syncthreads();
-  if (tid < nst) {
-    const double *qs = q + tid * P.na;
-    double best = qs[0];
-    int besta = 0;
-    for (int a = 1; a < P.na; ++a)
-      if (qs[a] > best) {  // the lowest index wins ties
-        best = qs[a];
-        besta = a;
-      }
-    pi[s0 + tid] = besta;
+  for (int64_t j = 0;; ++j) {
+    int ok;
+    const int64_t blk = xcd_block(j, P.n_blocks, ok);
+    if (!ok) break;
+    const int64_t s0 = blk * P.states_per_wg;
+    const int nst = (int)min((int64_t)P.states_per_wg, P.ns - s0);
+    block_q(P, v, s0, nst, rp, prod, q);
+    if (tid < nst) {
+      const double *qs = q + tid * P.na;
+      double best = qs[0];
+      int besta = 0;
+      for (int a = 1; a < P.na; ++a)
+        if (qs[a] > best) {  // the lowest index wins ties
+          best = qs[a];
+          besta = a;
+        }
+      pi[s0 + tid] = besta;
+    }
+    __syncthreads();
   }
 }
 

@@ -95,6 +95,8 @@ def load():
             "mdp_value_iterate": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp,
                                    C.c_size_t, vp, vp], C.c_int32),
             "mdp_policy": ([vp, P, C.POINTER(MdpModel), C.c_int32, vp, vp, vp], C.c_int32),
+            "mdp_ctx_profile": ([vp, C.c_int32], C.c_int32),
+            "mdp_ctx_profile_read": ([vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(lib, name)
@@ -105,7 +107,9 @@ def load():
 
 
 EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_error", "mdp_build_query",
-            "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_policy"]
+            "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_policy", "mdp_ctx_profile",
+            "mdp_ctx_profile_read"]
+MDP_KERNEL_BUILD, MDP_KERNEL_VI_SWEEP, MDP_KERNEL_POLICY, MDP_KERNEL_COPY = 0, 1, 2, 3
 
 
 def problem_struct(p: dict) -> MdpProblem:
@@ -193,6 +197,16 @@ def mdp_policy(ctx, problem: dict, model: dict, mission: int, v: torch.Tensor, p
     rc = load().mdp_policy(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, _ptr(v), _ptr(pi),
                            _stream_handle(stream))
     _check(ctx, rc, "mdp_policy")
+
+
+def mdp_ctx_profile(ctx, enable: bool) -> None:
+    _check(ctx, load().mdp_ctx_profile(ctx, 1 if enable else 0), "mdp_ctx_profile")
+
+
+def mdp_ctx_profile_read(ctx, kernel: int):
+    n, ms = C.c_int64(), C.c_double()
+    _check(ctx, load().mdp_ctx_profile_read(ctx, kernel, C.byref(n), C.byref(ms)), "mdp_ctx_profile_read")
+    return n.value, ms.value
 
 
 def stats_buffer(cls) -> torch.Tensor:
