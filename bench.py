@@ -52,6 +52,192 @@ def cpu_baseline(w, seconds: float = 12.0):
                        f"{dt:.1f} s on one host core")
 
 
+def _ev_ms(stream, fn, reps: int) -> float:
+    """Mean ms of fn() over reps runs, HIP events on `stream` around the runs."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_leg(pl, n_inst: int = 64, reps: int = 2) -> dict:
+    """The uneven 64-instance batch: one persistent build launch + one sweep launch per
+    iteration + policies, replayed from a HIP graph, against the same instances solved
+    one after another with the plain calls (build, value iteration, policy) on one stream."""
+    import torch
+
+    from paper_2109_00857_amd import mdp, workloads as W
+
+    t_gen = time.perf_counter()
+    ws = [W.batched_instance(i) for i in range(n_inst)]
+    t_gen = time.perf_counter() - t_gen
+    missions = [w.missions()[0] for w in ws]
+    envs = [pl.upload_env(w) for w in ws]
+    samples = sum(w.nominal_samples for w in ws)
+    b = mdp.Batch(pl, [w.problem for w in ws], envs, missions)
+    bs = b.build_checked()
+    assert all(x["status"] == mdp.MDP_OK for x in bs), bs
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.capture(stream=s)
+    s.synchronize()
+    b.replay(stream=s)  # warm
+    ms_batch = _ev_ms(s, lambda: b.replay(stream=s), reps)
+    bst, vst = b.stats()
+    assert all(x["status"] == mdp.MDP_OK for x in bst) and all(x["status"] == mdp.MDP_OK for x in vst)
+    nnz = [x["nnz"] for x in bst]
+    pi_batch = [t.clone() for t in b.pi]
+    b.close()
+    del b
+
+    # the same instances through the plain single-problem calls, back to back
+    models = [pl.alloc_model(w.problem, c) for w, c in zip(ws, nnz)]
+    scratch = torch.empty(max(mdp.mdp_build_query(w.problem)["scratch_bytes"] for w in ws), dtype=torch.uint8,
+                          device=pl.device)
+    vs = [torch.zeros(w.n_states, dtype=torch.float64, device=pl.device) for w in ws]
+    pis = [torch.empty(w.n_states, dtype=torch.int32, device=pl.device) for w in ws]
+    bstat = [mdp.stats_buffer(mdp.MdpBuildStats) for _ in ws]
+    vstat = [mdp.stats_buffer(mdp.MdpViStats) for _ in ws]
+
+    def plain_all():
+        for k, w in enumerate(ws):
+            mdp.mdp_build(pl.ctx, w.problem, envs[k], models[k], scratch, bstat[k], s)
+            vs[k].zero_()
+            mdp.mdp_value_iterate(pl.ctx, w.problem, models[k], missions[k], 1e-6, 100000, vs[k], scratch,
+                                  vstat[k], s)
+            mdp.mdp_policy(pl.ctx, w.problem, models[k], missions[k], vs[k], pis[k], s)
+
+    with torch.cuda.stream(s):
+        plain_all()  # warm
+        ms_plain = _ev_ms(s, plain_all, reps)
+    same = all(torch.equal(a, c) for a, c in zip(pis, pi_batch))
+    rows = sum(w.n_rows for w in ws)
+    out = dict(instances=n_inst, samples=samples, rows=rows, nnz=sum(nnz), generator_s=t_gen,
+               ms_batched_graph=ms_batch, ms_plain_sequential=ms_plain,
+               samples_per_s_batched=samples / (ms_batch / 1e3), samples_per_s_plain=samples / (ms_plain / 1e3),
+               speedup=ms_plain / ms_batch, policies_equal=bool(same),
+               sweeps_max=max(x["sweeps"] for x in vst))
+    del models, scratch, vs, pis
+    torch.cuda.empty_cache()
+    return out
+
+
+def _served_trace(seconds: float, rate: float, seed: int = 7):
+    """Poisson arrivals; 90 % uneven batched-mix requests, 10 % paper-shaped ones, each
+    request's seed 100000 + j and its mission uniform over the three."""
+    import numpy as np
+
+    from paper_2109_00857_amd import workloads as W
+
+    rng = np.random.default_rng(seed)
+    t, arr = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        arr.append(t)
+    reqs = []
+    for j in range(len(arr)):
+        if rng.random() < 0.1:
+            m = int(rng.integers(0, 3))
+            w = W.config2(seed=100000 + j, missions=(m,))
+            if m != W.MISSION_NET_ENERGY:
+                w.gbar = None
+        else:
+            w = W.batched_instance(j, base_seed=100000)
+            m = w.missions()[0]
+        reqs.append((w, m))
+    return arr, reqs
+
+
+def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
+    """The served trace through the continuous-batching server, then the same trace
+    through sequential plain solves (first come, first served, one at a time)."""
+    import numpy as np
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    t_gen = time.perf_counter()
+    arr, reqs = _served_trace(seconds, rate)
+    envs = [pl.upload_env(w) for w, _ in reqs]
+    t_gen = time.perf_counter() - t_gen
+    n = len(reqs)
+    samples = sum(w.nominal_samples for w, _ in reqs)
+
+    def stats(lat, wall):
+        a = np.array([lat[j] for j in range(n)]) * 1e3
+        return dict(p50_ms=float(np.percentile(a, 50)), p99_ms=float(np.percentile(a, 99)),
+                    mean_ms=float(a.mean()), max_ms=float(a.max()), wall_s=wall,
+                    requests_per_s=n / wall, samples_per_s=samples / wall)
+
+    s = torch.cuda.Stream()
+    srv = mdp.Server(pl, pool_bytes=int(pool_gib * (1 << 30)), max_inflight=64, sweeps_per_step=8, stream=s)
+    # warm the server's code paths on the first two requests (results discarded)
+    for j in range(min(2, n)):
+        srv.submit(-1 - j, reqs[j][0].problem, envs[j], reqs[j][1])
+    while srv.step():
+        pass
+    srv.poll()
+    lat, status = {}, {}
+    i = 0
+    t0 = time.perf_counter()
+    while len(lat) < n:
+        now = time.perf_counter() - t0
+        while i < n and arr[i] <= now:
+            srv.submit(i, reqs[i][0].problem, envs[i], reqs[i][1])
+            i += 1
+        if i - len(lat) > 0:
+            srv.step()
+        elif i < n:
+            time.sleep(max(0.0, arr[i] - (time.perf_counter() - t0)))
+        t = time.perf_counter() - t0
+        for rec in srv.poll():
+            lat[rec["tag"]] = t - arr[rec["tag"]]
+            status[rec["tag"]] = rec["status"]
+    wall_served = time.perf_counter() - t0
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    served = stats(lat, wall_served)
+    served["all_ok"] = all(v == mdp.MDP_OK for v in status.values())
+
+    # sequential plain solves of the same trace
+    lat2 = {}
+    bst, vst = mdp.stats_buffer(mdp.MdpBuildStats), mdp.stats_buffer(mdp.MdpViStats)
+    with torch.cuda.stream(s):
+        t0 = time.perf_counter()
+        for j, (w, m) in enumerate(reqs):
+            now = time.perf_counter() - t0
+            if now < arr[j]:
+                time.sleep(arr[j] - now)
+            p = dict(w.problem, mission_mask=1 << m)
+            sz = mdp.mdp_build_query(p)
+            model = pl.alloc_model(p, sz["nnz_upper"])
+            scratch = pl.scratch(p)
+            v = torch.zeros(sz["n_states"], dtype=torch.float64, device=pl.device)
+            pi = torch.empty(sz["n_states"], dtype=torch.int32, device=pl.device)
+            mdp.mdp_build(pl.ctx, p, envs[j], model, scratch, bst, s)
+            mdp.mdp_value_iterate(pl.ctx, p, model, m, 1e-6, 100000, v, scratch, vst, s)
+            mdp.mdp_policy(pl.ctx, p, model, m, v, pi, s)
+            pi_host = pi.to("cpu", non_blocking=False)
+            lat2[j] = time.perf_counter() - t0 - arr[j]
+            del model, scratch, v, pi, pi_host
+        wall_seq = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    seq = stats(lat2, wall_seq)
+    return dict(trace=f"Poisson {rate}/s for {seconds} s (seed 7): {n} requests, 90% uneven batched-mix, "
+                      f"10% paper-shaped, missions uniform", requests=n, samples=samples, generator_s=t_gen,
+                served=served, sequential_plain=seq,
+                p50_speedup=seq["p50_ms"] / served["p50_ms"], p99_speedup=seq["p99_ms"] / served["p99_ms"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +245,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--near-edge", action="store_true", help="also count near-edge samples")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-trace leg")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the served trace")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrival rate (per second)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the planner has no multi-GPU path",
@@ -176,6 +366,20 @@ def main():
         "roofline": dominant,
         "rooflines": {"build": roof_build, "vi_sweep": roof_vi},
     }
+    del model, scratch, vs, pis
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        try:
+            out["batched"] = batched_leg(pl)
+        except Exception as e:  # reported, never hides the main line
+            out["batched"] = {"error": repr(e)}
+    if not args.no_served:
+        try:
+            out["served"] = served_leg(pl, args.serve_seconds, args.serve_rate)
+            out["p50_ms_served"] = out["served"]["served"]["p50_ms"]
+            out["p99_ms_served"] = out["served"]["served"]["p99_ms"]
+        except Exception as e:
+            out["served"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w)
         out["cpu_baseline"] = cb

@@ -139,7 +139,8 @@ typedef struct mdp_vi_stats {
 
 typedef struct mdp_ctx mdp_ctx;
 
-/* Context bound to one HIP device. Holds no per-call state. */
+/* Context bound to one HIP device: small internal scratch, the last error
+ * text and the per-kernel timing records. */
 mdp_status mdp_ctx_create(int32_t device, mdp_ctx **out);
 mdp_status mdp_ctx_destroy(mdp_ctx *ctx);
 
@@ -186,6 +187,98 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
  * d_pi int32 [N_s]. */
 mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
                       int32_t mission, const double *d_v, int32_t *d_pi, void *stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems built and solved together (not in the paper: the
+ * batched form of the calls above). mdp_batch_create takes every pointer up
+ * front and uploads one device descriptor table, so build and solve only
+ * enqueue kernels and can be captured into a HIP graph:
+ *   - the build is one persistent launch over a work list of (problem, layer,
+ *     cell tile) items sorted by cost, each item's entries staged in a
+ *     bump-allocated pool of pool_entries 8-byte entries (0: 4 per row of the
+ *     batch), then a per-problem scan and one copy launch into each CSR;
+ *   - the solve runs one sweep launch per iteration over the state blocks of
+ *     every problem that has not converged (per-problem residual, done flag and
+ *     sweep count), then the greedy policy of each problem.
+ * Every problem's model, values and policy equal those of mdp_build /
+ * mdp_value_iterate / mdp_policy on it alone, bit for bit.
+ * Ownership: models, values (fp64 [N_s], v0 = 0 is written by the solve),
+ * policies and scratch are caller-owned device buffers; the batch owns only its
+ * descriptor table. Device-side errors appear in mdp_batch_stats:
+ * MDP_E_CAPACITY (model too small), MDP_E_SCRATCH (staging pool too small),
+ * MDP_E_SUBGRID. At most 1024 problems. */
+typedef struct mdp_batch mdp_batch;
+mdp_status mdp_batch_query(int32_t n, const mdp_problem *probs, int64_t pool_entries, size_t *scratch_bytes);
+mdp_status mdp_batch_create(mdp_ctx *ctx, int32_t n, const mdp_problem *probs, const mdp_env *envs,
+                            const mdp_model *models, const int32_t *missions, double *const *d_v,
+                            int32_t *const *d_pi, int64_t pool_entries, void *scratch, size_t scratch_bytes,
+                            mdp_batch **out);
+mdp_status mdp_batch_build(mdp_batch *b, void *stream);
+mdp_status mdp_batch_solve(mdp_batch *b, double tol, int32_t max_sweeps, void *stream);
+/* Copies the per-problem stats to the host (waits for the device). Either
+ * pointer may be NULL. */
+mdp_status mdp_batch_stats(mdp_batch *b, mdp_build_stats *build_stats, mdp_vi_stats *vi_stats);
+/* Record build + solve on `stream` (not the null stream) into a HIP graph
+ * owned by the batch; mdp_batch_replay launches it. */
+mdp_status mdp_batch_capture(mdp_batch *b, double tol, int32_t max_sweeps, void *stream);
+mdp_status mdp_batch_replay(mdp_batch *b, void *stream);
+mdp_status mdp_batch_destroy(mdp_batch *b);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of planning requests (not in the paper). Requests queue
+ * in arrival order; each mdp_server_step
+ *   1. admits queued requests in order while a slot is free and the pool holds
+ *      the request's footprint (mdp_server_footprint: model with the worst-case
+ *      nonzeros rows * min(N_sg, n_real), values, policy, and its share of the
+ *      build scratch);
+ *   2. builds every newly admitted request in one batched build launch and
+ *      gives the unused part of the worst-case reservation back to the pool;
+ *   3. runs up to sweeps_per_step synchronous sweeps over every admitted
+ *      request in one launch per sweep (requests joined at different sweeps);
+ *   4. retires each request that converged (or reached its sweep limit):
+ *      greedy policy, copies of the policy / values into the caller's host
+ *      buffers, completion record, pool space freed.
+ * Each request's model, values and policy equal those of mdp_build /
+ * mdp_value_iterate / mdp_policy on it alone, bit for bit. Only the requested
+ * mission's reward is built. The step waits for the device before returning.
+ * Ownership: the pool is a caller-owned device range; env arrays and h_pi /
+ * h_v (host, int32 / fp64 [N_s], may be NULL; pinned memory keeps the copies
+ * asynchronous) must stay valid until the request's completion is polled. */
+typedef struct mdp_server mdp_server;
+typedef struct mdp_server_config {
+  int32_t max_inflight;    /* requests admitted at once, 1..1024                */
+  int32_t sweeps_per_step; /* most sweeps a step enqueues, >= 1                 */
+  int32_t max_sweeps;      /* a request retires unconverged after this many     */
+  int32_t pad;
+  double tol;              /* residual below which a request has converged      */
+} mdp_server_config;
+typedef struct mdp_served {
+  int64_t tag;                   /* the submitter's tag                         */
+  int64_t nnz, samples;          /* model size and landings computed            */
+  int64_t admit_step, done_step; /* step numbers (1-based) of admission / retirement */
+  double residual;               /* last sweep's residual                       */
+  double v_start;                /* value of (t = 0, start cell)                */
+  int32_t status;                /* MDP_OK, a build error, or MDP_E_NOT_CONVERGED */
+  int32_t build_status;
+  int32_t sweeps, pad;
+} mdp_served;
+typedef struct mdp_server_state {
+  int32_t queued, in_flight, completed, pad;
+  int64_t pool_used, steps;
+} mdp_server_state;
+/* Pool bytes a request of problem p holds at admission. */
+mdp_status mdp_server_footprint(const mdp_problem *p, size_t *bytes);
+mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *pool, size_t pool_bytes,
+                             mdp_server **out);
+/* Queue a request (no device work). MDP_E_CAPACITY if it can never fit the pool. */
+mdp_status mdp_server_submit(mdp_server *srv, const mdp_problem *p, const mdp_env *env, int32_t mission,
+                             int32_t *h_pi, double *h_v, int64_t tag);
+/* One scheduler iteration on `stream`; n_active = queued + admitted afterwards. */
+mdp_status mdp_server_step(mdp_server *srv, void *stream, int32_t *n_active);
+/* Move up to max_out completion records (oldest first) into out. */
+mdp_status mdp_server_poll(mdp_server *srv, mdp_served *out, int32_t max_out, int32_t *n_out);
+mdp_status mdp_server_info(mdp_server *srv, mdp_server_state *out);
+mdp_status mdp_server_destroy(mdp_server *srv);
 
 /* Per-kernel timing. While enabled, HIP events are recorded on the caller's
  * stream around every launch of the kernels below; mdp_ctx_profile_read waits

@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -29,7 +31,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kStageBudget = size_t(4) << 30;  // staging bytes per build pass
-constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kLdsLimit = 160 * 1024 - 256;  // leaves room for a kernel's static LDS
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -86,7 +88,7 @@ const char *make_plan(const mdp_problem *p, Plan &pl)
   pl.nsg = pl.W * (2 * p->sub_hy + 1);
   pl.rows = (int64_t)p->nt * pl.nc * pl.na;
   pl.pack16 = true;  // n_real <= 65535, so two 16-bit counters fit a word
-  pl.kmax = p->n_modes <= 4 ? 4 : (p->n_modes <= 8 ? 8 : 16);
+  pl.kmax = p->n_modes <= 4 ? 4 : (p->n_modes <= 8 ? 8 : (p->n_modes <= 12 ? 12 : 16));
   const size_t fixed_lds = 2 * kMaxA * sizeof(float) + 16 * sizeof(uint32_t);
   bool ok = false;
   for (int rl = kBlock; rl >= 64 && !ok; rl /= 2) {
@@ -535,7 +537,7 @@ static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *
   V.cap = model->nnz_capacity;
   V.ns = (int64_t)p->nt * pl.nc;
   V.na = pl.na;
-  V.states_per_wg = kBlock / pl.na;
+  V.states_per_wg = 2 * kBlock / pl.na;
   V.n_blocks = (V.ns + V.states_per_wg - 1) / V.states_per_wg;
   V.n_wg = (int)std::min<int64_t>(V.n_blocks, 2048);
   V.inv_nr = 1.0 / (double)p->n_real;
@@ -565,7 +567,7 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   V.tol = tol;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  if ((e = launch_vi_init(V.st, s)) != hipSuccess) return hip_fail(ctx, e, "vi init");
+  if ((e = launch_vi_init(V.st, 1, s)) != hipSuccess) return hip_fail(ctx, e, "vi init");
   // The model is layered in time, so a positive tolerance is met after at most
   // nt + 1 sweeps (the last one has residual exactly 0): no host polling.
   int n = max_sweeps;
@@ -574,7 +576,7 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
     const double *vin = (k & 1) ? v_alt : d_v;
     double *vout = (k & 1) ? d_v : v_alt;
     Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
-    if ((e = launch_vi_sweep(V, vin, vout, k & 1, s)) != hipSuccess) return hip_fail(ctx, e, "vi sweep");
+    if ((e = launch_vi_sweep(V, vin, vout, s)) != hipSuccess) return hip_fail(ctx, e, "vi sweep");
   }
   if ((e = launch_vi_finish(V, d_v, v_alt, dstats, s)) != hipSuccess) return hip_fail(ctx, e, "vi finish");
   if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_vi_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -596,6 +598,1001 @@ mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model
   Timed tm(ctx, MDP_KERNEL_POLICY, (hipStream_t)stream);
   hipError_t e = launch_policy(V, d_v, d_pi, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "policy");
+  return MDP_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batches
+namespace {
+
+constexpr int kBatchViGrid = 2048;
+
+struct BatchLayout {
+  size_t st, bstats, ctr, vst, vstats, wg_res, pool, total;
+  std::vector<size_t> row_nnz, row_off, item_total, item_base, item_off, v_alt;
+};
+
+const char *batch_layout(int n, const mdp_problem *probs, int64_t pool_entries, std::vector<Plan> &plans,
+                         BatchLayout &L, int64_t &pool_cap)
+{
+  if (n < 1 || n > kMaxBatch) return "batch size must be in [1, 1024]";
+  plans.resize(n);
+  int64_t rows_all = 0;
+  for (int i = 0; i < n; ++i) {
+    if (const char *e = make_plan(&probs[i], plans[i])) return e;
+    rows_all += plans[i].rows;
+  }
+  pool_cap = pool_entries > 0 ? pool_entries : 4 * rows_all + 1024;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.st = take(sizeof(BuildState) * n);
+  L.bstats = take(sizeof(mdp_build_stats) * n);
+  L.ctr = take(64);
+  L.vst = take(sizeof(VIState) * n);
+  L.vstats = take(sizeof(mdp_vi_stats) * n);
+  L.wg_res = take(sizeof(double) * (size_t)kBatchViGrid * n);
+  L.row_nnz.resize(n);
+  L.row_off.resize(n);
+  L.item_total.resize(n);
+  L.item_base.resize(n);
+  L.item_off.resize(n);
+  L.v_alt.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const Plan &pl = plans[i];
+    const size_t items = (size_t)probs[i].nt * pl.tiles_per_layer;
+    L.row_nnz[i] = take(4 * (size_t)pl.rows);
+    L.row_off[i] = take(4 * (size_t)pl.rows);
+    L.item_total[i] = take(4 * items);
+    L.item_base[i] = take(8 * items);
+    L.item_off[i] = take(8 * items);
+    L.v_alt[i] = take(8 * (size_t)probs[i].nt * pl.nc);
+  }
+  L.pool = take(8 * (size_t)pool_cap);
+  L.total = off;
+  return nullptr;
+}
+
+// Per-problem scratch of a batched build, device addresses.
+struct BuildScratch {
+  BuildState *st;
+  uint32_t *row_nnz, *row_off, *item_total;
+  int64_t *item_base, *item_off;
+};
+
+// Build descriptor of one problem of a batch, its action tables (htab:
+// 2 * kMaxA floats for d_tab) and its (cost, item) work list entries.
+const char *batch_build_desc(int inst, const mdp_problem *p, const mdp_env *env, const mdp_model &M, const Plan &pl,
+                             const BuildScratch &B, float *d_tab, float *htab, BatchBuildDesc &D,
+                             std::vector<std::pair<double, BatchItem>> &items)
+{
+  if (const char *m = check_env(p, env)) return m;
+  memset(&D, 0, sizeof(D));
+  ActionTables T;
+  fill_params(p, env, &M, pl, D.P, T);
+  double mx = 0.0, my = 0.0;
+  for (int a = 0; a < pl.na; ++a) {
+    mx = std::max(mx, fabs((double)T.hx[a]));
+    my = std::max(my, fabs((double)T.hy[a]));
+  }
+  if (safe_speed(p->sub_hx, mx, 1.0, p->nx) < 0.0f || safe_speed(p->sub_hy, my, 1.0, p->ny) < 0.0f)
+    return "the sub-grid cannot hold the agent's own displacement";
+  memcpy(htab, T.hx, sizeof(T.hx));
+  memcpy(htab + kMaxA, T.hy, sizeof(T.hy));
+  D.P.tab = d_tab;
+  D.st = B.st;
+  D.row_nnz = B.row_nnz;
+  D.row_off = B.row_off;
+  D.item_total = B.item_total;
+  D.item_base = B.item_base;
+  D.item_off = B.item_off;
+  D.M = ModelOut{M.row_ptr, M.col, M.cnt, M.nnz_capacity};
+  D.n_items = (int64_t)p->nt * pl.tiles_per_layer;
+  D.near_asked = (p->flags & MDP_FLAG_NEAR_EDGE) ? 1 : 0;
+  for (int t = 0; t < p->nt; ++t)
+    for (int tile = 0; tile < pl.tiles_per_layer; ++tile) {
+      const int ncell = std::min(pl.cells_per_tile, pl.nc - tile * pl.cells_per_tile);
+      const double cost = (double)ncell * p->n_real * (pl.na + 0.25 * p->n_modes);
+      items.push_back({cost, BatchItem{inst, t, tile, 0}});
+    }
+  return nullptr;
+}
+
+// Work list in descending cost (ties keep problem, layer, tile order).
+std::vector<BatchItem> sort_items(std::vector<std::pair<double, BatchItem>> &items)
+{
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<double, BatchItem> &x, const std::pair<double, BatchItem> &y) {
+                     return x.first > y.first;
+                   });
+  std::vector<BatchItem> flat(items.size());
+  for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].second;
+  return flat;
+}
+
+// Solve descriptor of one problem of a batch.
+void batch_vi_desc(const mdp_problem *p, const mdp_model &M, const Plan &pl, int mission, double *v, double *v_alt,
+                   int32_t *pi, VIState *st, BatchVIDesc &V)
+{
+  memset(&V, 0, sizeof(V));
+  int slot = 0;
+  for (int m = 0; m < mission; ++m) slot += (int)(p->mission_mask >> m & 1u);
+  V.P.row_ptr = M.row_ptr;
+  V.P.col = M.col;
+  V.P.cnt = M.cnt;
+  V.P.R = M.reward + (int64_t)slot * pl.rows;
+  V.P.cap = M.nnz_capacity;
+  V.P.ns = (int64_t)p->nt * pl.nc;
+  V.P.na = pl.na;
+  V.P.states_per_wg = 2 * kBlock / pl.na;
+  V.P.n_blocks = (V.P.ns + V.P.states_per_wg - 1) / V.P.states_per_wg;
+  V.P.n_wg = kBatchViGrid;
+  V.P.inv_nr = 1.0 / (double)p->n_real;
+  V.st = st;
+  V.P.st = st;
+  V.v = v;
+  V.v_alt = v_alt;
+  V.pi = pi;
+}
+
+// Persistent-build grid: resident workgroups of the device, at most one per item.
+hipError_t batch_build_grid(int kmax, bool near, size_t lds, int n_items, int *grid)
+{
+  int per_cu = 0;
+  hipError_t e = batch_build_occupancy(kmax, near, lds, &per_cu);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidValue;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  *grid = std::max(1, std::min(per_cu * std::max(cus, 1), n_items));
+  return hipSuccess;
+}
+
+}  // namespace
+
+struct mdp_batch {
+  mdp_ctx *ctx = nullptr;
+  int n = 0;
+  int kmax = 4;
+  bool near = false;
+  size_t lds_max = 0;
+  int grid_build = 0;
+  int n_items = 0;
+  int max_nt = 0;
+  int64_t pool_cap = 0;
+  char *scratch = nullptr;
+  BatchLayout L;
+  BatchBuildDesc *d_bdesc = nullptr;
+  BatchVIDesc *d_vdesc = nullptr;
+  BatchItem *d_items = nullptr;
+  float *d_tabs = nullptr;
+  int64_t *d_block_start = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+extern "C" {
+
+mdp_status mdp_batch_query(int32_t n, const mdp_problem *probs, int64_t pool_entries, size_t *scratch_bytes)
+{
+  if (!probs || !scratch_bytes) return MDP_E_INVALID;
+  std::vector<Plan> plans;
+  BatchLayout L;
+  int64_t cap;
+  if (batch_layout(n, probs, pool_entries, plans, L, cap)) return MDP_E_INVALID;
+  *scratch_bytes = L.total;
+  return MDP_OK;
+}
+
+static void batch_free(mdp_batch *b)
+{
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->d_bdesc) (void)hipFree(b->d_bdesc);
+  if (b->d_vdesc) (void)hipFree(b->d_vdesc);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_tabs) (void)hipFree(b->d_tabs);
+  if (b->d_block_start) (void)hipFree(b->d_block_start);
+  delete b;
+}
+
+mdp_status mdp_batch_create(mdp_ctx *ctx, int32_t n, const mdp_problem *probs, const mdp_env *envs,
+                            const mdp_model *models, const int32_t *missions, double *const *d_v,
+                            int32_t *const *d_pi, int64_t pool_entries, void *scratch, size_t scratch_bytes,
+                            mdp_batch **out)
+{
+  if (!ctx || !probs || !envs || !models || !missions || !d_v || !d_pi || !out) return MDP_E_INVALID;
+  *out = nullptr;
+  std::vector<Plan> plans;
+  BatchLayout L;
+  int64_t pool_cap = 0;
+  if (const char *e = batch_layout(n, probs, pool_entries, plans, L, pool_cap)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  if (!is_device_ptr(scratch) || scratch_bytes < L.total) {
+    set_err(ctx, "batch scratch needs %zu device bytes", L.total);
+    return MDP_E_SCRATCH;
+  }
+  std::vector<BatchBuildDesc> bd(n);
+  std::vector<BatchVIDesc> vd(n);
+  std::vector<float> tabs((size_t)n * 2 * kMaxA, 0.0f);
+  std::vector<int64_t> block_start(n + 1, 0);
+  std::vector<std::pair<double, BatchItem>> items;
+  mdp_batch *b = new mdp_batch();
+  b->ctx = ctx;
+  b->n = n;
+  b->L = L;
+  b->pool_cap = pool_cap;
+  b->scratch = (char *)scratch;
+  char *sc = (char *)scratch;
+  hipError_t e = hipMalloc((void **)&b->d_tabs, sizeof(float) * tabs.size());
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(ctx, e, "batch tables");
+  }
+  for (int i = 0; i < n; ++i) {
+    const mdp_problem *p = &probs[i];
+    const Plan &pl = plans[i];
+    const mdp_model &M = models[i];
+    if (!is_device_ptr(M.row_ptr) || !is_device_ptr(M.reward) || !is_device_ptr(M.col) || !is_device_ptr(M.cnt) ||
+        !is_device_ptr(d_v[i]) || !is_device_ptr(d_pi[i])) {
+      set_err(ctx, "problem %d: model, value and policy buffers must be device pointers", i);
+      batch_free(b);
+      return MDP_E_INVALID;
+    }
+    const int mission = missions[i];
+    if (mission < 0 || mission > 2 || !(p->mission_mask >> mission & 1u)) {
+      set_err(ctx, "problem %d: mission %d is not built", i, mission);
+      batch_free(b);
+      return MDP_E_INVALID;
+    }
+    const BuildScratch B{(BuildState *)(sc + L.st) + i,         (uint32_t *)(sc + L.row_nnz[i]),
+                         (uint32_t *)(sc + L.row_off[i]),       (uint32_t *)(sc + L.item_total[i]),
+                         (int64_t *)(sc + L.item_base[i]),      (int64_t *)(sc + L.item_off[i])};
+    if (const char *m = batch_build_desc(i, p, &envs[i], M, pl, B, b->d_tabs + (size_t)i * 2 * kMaxA,
+                                         &tabs[(size_t)i * 2 * kMaxA], bd[i], items)) {
+      set_err(ctx, "problem %d: %s", i, m);
+      batch_free(b);
+      return MDP_E_INVALID;
+    }
+    b->near = b->near || bd[i].near_asked;
+    b->kmax = std::max(b->kmax, pl.kmax);
+    b->lds_max = std::max(b->lds_max, pl.lds);
+    b->max_nt = std::max(b->max_nt, p->nt);
+    batch_vi_desc(p, M, pl, mission, d_v[i], (double *)(sc + L.v_alt[i]), d_pi[i], (VIState *)(sc + L.vst) + i,
+                  vd[i]);
+    block_start[i + 1] = block_start[i] + vd[i].P.n_blocks;
+  }
+  std::vector<BatchItem> flat = sort_items(items);
+  b->n_items = (int)flat.size();
+  if ((e = batch_build_grid(b->kmax, b->near, b->lds_max, b->n_items, &b->grid_build)) != hipSuccess) {
+    batch_free(b);
+    return hip_fail(ctx, e, "batch occupancy");
+  }
+  if ((e = hipMalloc((void **)&b->d_bdesc, sizeof(BatchBuildDesc) * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&b->d_vdesc, sizeof(BatchVIDesc) * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&b->d_items, sizeof(BatchItem) * flat.size())) != hipSuccess ||
+      (e = hipMalloc((void **)&b->d_block_start, sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = hipMemcpy(b->d_bdesc, bd.data(), sizeof(BatchBuildDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_vdesc, vd.data(), sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_items, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_block_start, block_start.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(b->d_tabs, tabs.data(), sizeof(float) * tabs.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    batch_free(b);
+    return hip_fail(ctx, e, "batch descriptors");
+  }
+  *out = b;
+  return MDP_OK;
+}
+
+mdp_status mdp_batch_build(mdp_batch *b, void *stream)
+{
+  if (!b) return MDP_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  char *sc = b->scratch;
+  unsigned int *counter = (unsigned int *)(sc + b->L.ctr);
+  unsigned long long *pool_top = (unsigned long long *)(sc + b->L.ctr + 8);
+  uint64_t *pool = (uint64_t *)(sc + b->L.pool);
+  hipError_t e;
+  if ((e = launch_batch_build_init(b->d_bdesc, b->n, counter, pool_top, s)) != hipSuccess)
+    return hip_fail(b->ctx, e, "batch init");
+  {
+    Timed tm(b->ctx, MDP_KERNEL_BUILD, s);
+    if ((e = launch_batch_build(b->d_bdesc, b->d_items, b->n_items, counter, pool, pool_top, b->pool_cap, b->kmax,
+                                b->near, b->lds_max, b->grid_build, s)) != hipSuccess)
+      return hip_fail(b->ctx, e, "batch build");
+  }
+  if ((e = launch_batch_scan(b->d_bdesc, b->n, s)) != hipSuccess) return hip_fail(b->ctx, e, "batch scan");
+  {
+    Timed tm(b->ctx, MDP_KERNEL_COPY, s);
+    if ((e = launch_batch_copy(b->d_bdesc, b->d_items, b->n_items, pool, s)) != hipSuccess)
+      return hip_fail(b->ctx, e, "batch copy");
+  }
+  if ((e = launch_batch_finalize(b->d_bdesc, b->n, (mdp_build_stats *)(sc + b->L.bstats), s)) != hipSuccess)
+    return hip_fail(b->ctx, e, "batch finalize");
+  return MDP_OK;
+}
+
+mdp_status mdp_batch_solve(mdp_batch *b, double tol, int32_t max_sweeps, void *stream)
+{
+  if (!b || max_sweeps < 0) return MDP_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  char *sc = b->scratch;
+  double *wg_res = (double *)(sc + b->L.wg_res);
+  hipError_t e;
+  if ((e = launch_vi_init((VIState *)(sc + b->L.vst), b->n, s)) != hipSuccess) return hip_fail(b->ctx, e, "vi init");
+  int sweeps = max_sweeps;
+  if (tol > 0.0) sweeps = std::min(sweeps, b->max_nt + 1);
+  for (int k = 0; k < sweeps; ++k) {
+    Timed tm(b->ctx, MDP_KERNEL_VI_SWEEP, s);
+    if ((e = launch_vi_sweep_batched(b->d_vdesc, b->n, b->d_block_start, wg_res, kBatchViGrid, s)) !=
+        hipSuccess)
+      return hip_fail(b->ctx, e, "batch sweep");
+    if ((e = launch_vi_close_batched(b->d_vdesc, b->n, kBatchViGrid, wg_res, tol, s)) != hipSuccess)
+      return hip_fail(b->ctx, e, "batch close");
+  }
+  if ((e = launch_vi_finish_batched(b->d_vdesc, b->n, (mdp_vi_stats *)(sc + b->L.vstats), s)) != hipSuccess)
+    return hip_fail(b->ctx, e, "batch finish");
+  Timed tm(b->ctx, MDP_KERNEL_POLICY, s);
+  if ((e = launch_policy_batched(b->d_vdesc, b->n, b->d_block_start, kBatchViGrid, s)) != hipSuccess)
+    return hip_fail(b->ctx, e, "batch policy");
+  return MDP_OK;
+}
+
+mdp_status mdp_batch_stats(mdp_batch *b, mdp_build_stats *build_stats, mdp_vi_stats *vi_stats)
+{
+  if (!b) return MDP_E_INVALID;
+  hipError_t e;
+  if (build_stats &&
+      (e = hipMemcpy(build_stats, b->scratch + b->L.bstats, sizeof(mdp_build_stats) * b->n, hipMemcpyDeviceToHost)) !=
+          hipSuccess)
+    return hip_fail(b->ctx, e, "batch stats");
+  if (vi_stats &&
+      (e = hipMemcpy(vi_stats, b->scratch + b->L.vstats, sizeof(mdp_vi_stats) * b->n, hipMemcpyDeviceToHost)) !=
+          hipSuccess)
+    return hip_fail(b->ctx, e, "batch stats");
+  return MDP_OK;
+}
+
+mdp_status mdp_batch_capture(mdp_batch *b, double tol, int32_t max_sweeps, void *stream)
+{
+  if (!b || !stream) return MDP_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  const bool prof = b->ctx->profiling;
+  b->ctx->profiling = false;  // no event records inside the graph
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    b->ctx->profiling = prof;
+    return hip_fail(b->ctx, e, "begin capture");
+  }
+  mdp_status rc = mdp_batch_build(b, stream);
+  if (rc == MDP_OK) rc = mdp_batch_solve(b, tol, max_sweeps, stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  b->ctx->profiling = prof;
+  if (rc != MDP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(b->ctx, e, "end capture");
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->gexec = nullptr;
+    return hip_fail(b->ctx, e, "graph instantiate");
+  }
+  return MDP_OK;
+}
+
+mdp_status mdp_batch_replay(mdp_batch *b, void *stream)
+{
+  if (!b || !b->gexec) return MDP_E_INVALID;
+  hipError_t e = hipGraphLaunch(b->gexec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(b->ctx, e, "graph launch");
+  return MDP_OK;
+}
+
+mdp_status mdp_batch_destroy(mdp_batch *b)
+{
+  if (!b) return MDP_E_INVALID;
+  batch_free(b);
+  return MDP_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== serving
+namespace {
+
+// First-fit allocator over one caller-owned device range (host bookkeeping only).
+class RangeAlloc {
+ public:
+  void reset(size_t cap)
+  {
+    free_.clear();
+    if (cap) free_[0] = cap;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t &off)
+  {
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        off = it->first;
+        const size_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        used_ += bytes;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t bytes)
+  {
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  // Keep the first new_bytes of a block of old_bytes; the tail becomes free.
+  void shrink(size_t off, size_t old_bytes, size_t new_bytes)
+  {
+    const size_t a = align_up(std::max<size_t>(old_bytes, 1)), b = align_up(std::max<size_t>(new_bytes, 1));
+    if (b < a) release(off + b, a - b);
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length, disjoint and non-adjacent
+  size_t used_ = 0;
+};
+
+struct Block {
+  size_t off = 0, len = 0;
+  bool live = false;
+};
+
+// Pool bytes a request holds from admission until its build is checked:
+// model with the worst-case nonzeros, values, policy, sweep state, and its
+// share of the build scratch and staging pool.
+struct ReqSizes {
+  int64_t rows, ns, cap;
+  size_t keep, col, cnt, build;
+};
+
+ReqSizes req_sizes(const mdp_problem *p, const Plan &pl)
+{
+  ReqSizes z;
+  z.rows = pl.rows;
+  z.ns = (int64_t)p->nt * pl.nc;
+  z.cap = pl.rows * (int64_t)std::min(pl.nsg, p->n_real);
+  z.keep = align_up(8 * (size_t)(z.rows + 1)) + align_up(4 * (size_t)z.rows) + 2 * align_up(8 * (size_t)z.ns) +
+           align_up(4 * (size_t)z.ns) + align_up(sizeof(VIState));
+  z.col = align_up(4 * (size_t)z.cap);
+  z.cnt = align_up(2 * (size_t)z.cap);
+  const size_t items = (size_t)p->nt * pl.tiles_per_layer;
+  z.build = align_up(sizeof(BuildState)) + align_up(sizeof(mdp_build_stats)) + 2 * align_up(4 * (size_t)z.rows) +
+            align_up(4 * items) + 2 * align_up(8 * items) + align_up(8 * (size_t)z.cap);
+  return z;
+}
+
+struct ServeReq {
+  int64_t tag = 0;
+  mdp_problem p{};
+  mdp_env env{};
+  int mission = 0;
+  int32_t *h_pi = nullptr;
+  double *h_v = nullptr;
+  Plan pl{};
+  ReqSizes z{};
+  Block keep, col, cnt;
+  int64_t model_cap = 0;  // col / cnt entries held: worst case until the build is checked
+  int sweeps = 0;         // sweeps enqueued since admission
+  int limit = 0;   // sweeps after which the request retires in any case
+  mdp_served res{};
+  // addresses inside the pool (valid while admitted)
+  int64_t *row_ptr = nullptr;
+  float *reward = nullptr;
+  double *v = nullptr, *v_alt = nullptr;
+  int32_t *pi = nullptr;
+  VIState *st = nullptr;
+  int32_t *colp = nullptr;
+  uint16_t *cntp = nullptr;
+};
+
+}  // namespace
+
+struct mdp_server {
+  mdp_ctx *ctx = nullptr;
+  mdp_server_config cfg{};
+  char *pool = nullptr;
+  size_t pool_bytes = 0;
+  RangeAlloc alloc;
+  std::deque<ServeReq *> queue;
+  std::vector<ServeReq *> running;
+  std::vector<mdp_served> done;
+  int64_t step_no = 0;
+  // device tables, sized for cfg.max_inflight problems
+  BatchBuildDesc *d_bdesc = nullptr;
+  BatchVIDesc *d_vrun = nullptr, *d_vret = nullptr;
+  int64_t *d_bs_run = nullptr, *d_bs_ret = nullptr;
+  double *d_wg_res = nullptr;
+  mdp_vi_stats *d_vstat = nullptr;
+  float *d_tabs = nullptr;
+  BatchItem *d_items = nullptr;
+  size_t items_cap = 0;
+  unsigned int *d_ctr = nullptr;  // work counter + staging pool top
+};
+
+namespace {
+
+void serve_free_all(mdp_server *S)
+{
+  for (ServeReq *r : S->queue) delete r;
+  for (ServeReq *r : S->running) delete r;
+  void *bufs[] = {S->d_bdesc, S->d_vrun, S->d_vret, S->d_bs_run, S->d_bs_ret,
+                  S->d_wg_res, S->d_vstat, S->d_tabs, S->d_items, S->d_ctr};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  delete S;
+}
+
+bool take(RangeAlloc &A, Block &b, size_t len)
+{
+  b.len = len;
+  b.live = A.alloc(len, b.off);
+  return b.live;
+}
+
+void give(RangeAlloc &A, Block &b)
+{
+  if (b.live) A.release(b.off, b.len);
+  b.live = false;
+}
+
+// Reserve the model blocks of r and point its buffers into the pool.
+bool reserve(mdp_server *S, ServeReq *r)
+{
+  if (!take(S->alloc, r->keep, r->z.keep)) return false;
+  if (!take(S->alloc, r->col, r->z.col)) {
+    give(S->alloc, r->keep);
+    return false;
+  }
+  if (!take(S->alloc, r->cnt, r->z.cnt)) {
+    give(S->alloc, r->col);
+    give(S->alloc, r->keep);
+    return false;
+  }
+  char *k = S->pool + r->keep.off;
+  size_t o = 0;
+  r->row_ptr = (int64_t *)(k + o);
+  o += align_up(8 * (size_t)(r->z.rows + 1));
+  r->reward = (float *)(k + o);
+  o += align_up(4 * (size_t)r->z.rows);
+  r->v = (double *)(k + o);
+  o += align_up(8 * (size_t)r->z.ns);
+  r->v_alt = (double *)(k + o);
+  o += align_up(8 * (size_t)r->z.ns);
+  r->pi = (int32_t *)(k + o);
+  o += align_up(4 * (size_t)r->z.ns);
+  r->st = (VIState *)(k + o);
+  r->colp = (int32_t *)(S->pool + r->col.off);
+  r->cntp = (uint16_t *)(S->pool + r->cnt.off);
+  r->model_cap = r->z.cap;
+  return true;
+}
+
+void unreserve(mdp_server *S, ServeReq *r)
+{
+  give(S->alloc, r->cnt);
+  give(S->alloc, r->col);
+  give(S->alloc, r->keep);
+}
+
+mdp_model req_model(const ServeReq *r)
+{
+  return mdp_model{r->row_ptr, r->colp, r->cntp, r->reward, r->model_cap};
+}
+
+size_t build_block_bytes(const std::vector<ServeReq *> &fresh)
+{
+  size_t b = align_up(64);  // work counter and staging pool top
+  for (const ServeReq *r : fresh) b += r->z.build;
+  return b;
+}
+
+// Upload descriptors and enqueue the batched build of the freshly admitted
+// requests; build statistics land in bstats (device, one per request).
+mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char *blk, hipStream_t s,
+                       mdp_build_stats **bstats_out)
+{
+  const int n = (int)fresh.size();
+  std::vector<BatchBuildDesc> bd(n);
+  std::vector<float> tabs((size_t)n * 2 * kMaxA, 0.0f);
+  std::vector<std::pair<double, BatchItem>> items;
+  size_t o = align_up(64);
+  unsigned int *counter = (unsigned int *)blk;
+  unsigned long long *pool_top = (unsigned long long *)(blk + 8);
+  // per-request scratch first, staging pool entries of every request last
+  std::vector<BuildScratch> B(n);
+  mdp_build_stats *bstats = nullptr;
+  int64_t pool_cap = 0;
+  bool near = false;
+  int kmax = 4;
+  size_t lds = 0;
+  {
+    BuildState *st = (BuildState *)(blk + o);
+    o += align_up(sizeof(BuildState) * n);
+    bstats = (mdp_build_stats *)(blk + o);
+    o += align_up(sizeof(mdp_build_stats) * n);
+    for (int i = 0; i < n; ++i) {
+      const ServeReq *r = fresh[i];
+      const size_t items_i = (size_t)r->p.nt * r->pl.tiles_per_layer;
+      B[i].st = st + i;
+      B[i].row_nnz = (uint32_t *)(blk + o);
+      o += align_up(4 * (size_t)r->z.rows);
+      B[i].row_off = (uint32_t *)(blk + o);
+      o += align_up(4 * (size_t)r->z.rows);
+      B[i].item_total = (uint32_t *)(blk + o);
+      o += align_up(4 * items_i);
+      B[i].item_base = (int64_t *)(blk + o);
+      o += align_up(8 * items_i);
+      B[i].item_off = (int64_t *)(blk + o);
+      o += align_up(8 * items_i);
+      pool_cap += r->z.cap;
+    }
+  }
+  uint64_t *pool = (uint64_t *)(blk + o);
+  for (int i = 0; i < n; ++i) {
+    ServeReq *r = fresh[i];
+    const mdp_model M = req_model(r);
+    if (const char *m = batch_build_desc(i, &r->p, &r->env, M, r->pl, B[i], S->d_tabs + (size_t)i * 2 * kMaxA,
+                                         &tabs[(size_t)i * 2 * kMaxA], bd[i], items)) {
+      set_err(S->ctx, "request %lld: %s", (long long)r->tag, m);
+      return MDP_E_INVALID;
+    }
+    near = near || bd[i].near_asked;
+    kmax = std::max(kmax, r->pl.kmax);
+    lds = std::max(lds, r->pl.lds);
+  }
+  std::vector<BatchItem> flat = sort_items(items);
+  hipError_t e;
+  if (flat.size() > S->items_cap) {
+    if (S->d_items) (void)hipFree(S->d_items);
+    S->d_items = nullptr;
+    S->items_cap = 0;
+    if ((e = hipMalloc((void **)&S->d_items, sizeof(BatchItem) * flat.size())) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve items");
+    S->items_cap = flat.size();
+  }
+  int grid = 1;
+  if ((e = batch_build_grid(kmax, near, lds, (int)flat.size(), &grid)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve occupancy");
+  if ((e = hipMemcpyAsync(S->d_bdesc, bd.data(), sizeof(BatchBuildDesc) * n, hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(S->d_tabs, tabs.data(), sizeof(float) * tabs.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(S->d_items, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess)
+    return hip_fail(S->ctx, e, "serve descriptors");
+  // pageable sources: make sure the copies have read them before they go away
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(S->ctx, e, "serve sync");
+  if ((e = launch_batch_build_init(S->d_bdesc, n, counter, pool_top, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve build init");
+  {
+    Timed tm(S->ctx, MDP_KERNEL_BUILD, s);
+    if ((e = launch_batch_build(S->d_bdesc, S->d_items, (int)flat.size(), counter, pool, pool_top, pool_cap, kmax,
+                                near, lds, grid, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve build");
+  }
+  if ((e = launch_batch_scan(S->d_bdesc, n, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve scan");
+  {
+    Timed tm(S->ctx, MDP_KERNEL_COPY, s);
+    if ((e = launch_batch_copy(S->d_bdesc, S->d_items, (int)flat.size(), pool, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve copy");
+  }
+  if ((e = launch_batch_finalize(S->d_bdesc, n, bstats, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve finalize");
+  *bstats_out = bstats;
+  return MDP_OK;
+}
+
+// Upload the solve descriptors of reqs into D / bstart (device).
+mdp_status upload_vi(mdp_server *S, const std::vector<ServeReq *> &reqs, BatchVIDesc *D, int64_t *bstart,
+                     hipStream_t s)
+{
+  const int n = (int)reqs.size();
+  std::vector<BatchVIDesc> vd(n);
+  std::vector<int64_t> bs(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    ServeReq *r = reqs[i];
+    batch_vi_desc(&r->p, req_model(r), r->pl, r->mission, r->v, r->v_alt, r->pi, r->st, vd[i]);
+    bs[i + 1] = bs[i] + vd[i].P.n_blocks;
+  }
+  hipError_t e;
+  if ((e = hipMemcpyAsync(D, vd.data(), sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(bstart, bs.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve descriptors");
+  return MDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdp_status mdp_server_footprint(const mdp_problem *p, size_t *bytes)
+{
+  if (!bytes) return MDP_E_INVALID;
+  Plan pl;
+  if (make_plan(p, pl)) return MDP_E_INVALID;
+  const ReqSizes z = req_sizes(p, pl);
+  *bytes = z.keep + z.col + z.cnt + z.build + align_up(64);
+  return MDP_OK;
+}
+
+mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *pool, size_t pool_bytes,
+                             mdp_server **out)
+{
+  if (!ctx || !cfg || !out) return MDP_E_INVALID;
+  *out = nullptr;
+  if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxBatch || cfg->sweeps_per_step < 1 || cfg->max_sweeps < 1) {
+    set_err(ctx, "max_inflight must be in [1, 1024], sweeps_per_step and max_sweeps >= 1");
+    return MDP_E_INVALID;
+  }
+  if (!is_device_ptr(pool) || pool_bytes < kAlign) {
+    set_err(ctx, "the model pool must be device memory");
+    return MDP_E_INVALID;
+  }
+  mdp_server *S = new mdp_server();
+  S->ctx = ctx;
+  S->cfg = *cfg;
+  S->pool = (char *)pool;
+  S->pool_bytes = pool_bytes / kAlign * kAlign;
+  S->alloc.reset(S->pool_bytes);
+  const size_t n = (size_t)cfg->max_inflight;
+  hipError_t e;
+  if ((e = hipMalloc((void **)&S->d_bdesc, sizeof(BatchBuildDesc) * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_vret, sizeof(BatchVIDesc) * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_bs_run, sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_bs_ret, sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_wg_res, sizeof(double) * kBatchViGrid * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_vstat, sizeof(mdp_vi_stats) * n)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_tabs, sizeof(float) * 2 * kMaxA * n)) != hipSuccess) {
+    serve_free_all(S);
+    return hip_fail(ctx, e, "server tables");
+  }
+  *out = S;
+  return MDP_OK;
+}
+
+mdp_status mdp_server_submit(mdp_server *S, const mdp_problem *p, const mdp_env *env, int32_t mission,
+                             int32_t *h_pi, double *h_v, int64_t tag)
+{
+  if (!S || !p || !env) return MDP_E_INVALID;
+  if (mission < 0 || mission > 2) {
+    set_err(S->ctx, "mission must be 0, 1 or 2");
+    return MDP_E_INVALID;
+  }
+  ServeReq *r = new ServeReq();
+  r->tag = tag;
+  r->p = *p;
+  r->p.mission_mask = 1u << mission;  // one reward block: the requested mission
+  r->env = *env;
+  r->mission = mission;
+  r->h_pi = h_pi;
+  r->h_v = h_v;
+  if (const char *m = make_plan(&r->p, r->pl)) {
+    set_err(S->ctx, "request %lld: %s", (long long)tag, m);
+    delete r;
+    return MDP_E_INVALID;
+  }
+  if (const char *m = check_env(&r->p, env)) {
+    set_err(S->ctx, "request %lld: %s", (long long)tag, m);
+    delete r;
+    return MDP_E_INVALID;
+  }
+  r->z = req_sizes(&r->p, r->pl);
+  if (r->z.keep + r->z.col + r->z.cnt + r->z.build + align_up(64) > S->pool_bytes) {
+    set_err(S->ctx, "request %lld needs more than the whole pool", (long long)tag);
+    delete r;
+    return MDP_E_CAPACITY;
+  }
+  r->limit = S->cfg.max_sweeps;
+  if (S->cfg.tol > 0.0) r->limit = std::min(r->limit, r->p.nt + 1);
+  r->res.tag = tag;
+  S->queue.push_back(r);
+  return MDP_OK;
+}
+
+mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
+{
+  if (!S) return MDP_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  mdp_status rc;
+  ++S->step_no;
+  // ---- admission (FIFO): model blocks of each request plus one build block
+  // for all requests admitted in this step
+  std::vector<ServeReq *> fresh;
+  Block bblk;
+  while (!S->queue.empty() && (int)(S->running.size() + fresh.size()) < S->cfg.max_inflight) {
+    ServeReq *r = S->queue.front();
+    const size_t prev_len = bblk.len;
+    give(S->alloc, bblk);
+    bool ok = reserve(S, r);
+    if (ok) {
+      fresh.push_back(r);
+      ok = take(S->alloc, bblk, build_block_bytes(fresh));
+      if (!ok) {
+        fresh.pop_back();
+        unreserve(S, r);
+      }
+    }
+    if (!ok) {
+      if (prev_len && !take(S->alloc, bblk, prev_len)) {  // the range just freed
+        set_err(S->ctx, "serve pool bookkeeping");
+        return MDP_E_HIP;
+      }
+      break;
+    }
+    r->res.admit_step = S->step_no;
+    S->queue.pop_front();
+  }
+  mdp_build_stats *d_bstats = nullptr;
+  if (!fresh.empty()) {
+    if ((rc = serve_build(S, fresh, S->pool + bblk.off, s, &d_bstats)) != MDP_OK) return rc;
+  }
+  // ---- solve: every admitted request, fresh ones last (cold start)
+  const int n_old = (int)S->running.size();
+  S->running.insert(S->running.end(), fresh.begin(), fresh.end());
+  const int n_run = (int)S->running.size();
+  std::vector<mdp_build_stats> hb(fresh.size());
+  if (n_run > 0) {
+    if ((rc = upload_vi(S, S->running, S->d_vrun, S->d_bs_run, s)) != MDP_OK) return rc;
+    if ((e = launch_vi_reset_batched(S->d_vrun + n_old, n_run - n_old, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve reset");
+    int k = S->cfg.sweeps_per_step;
+    for (ServeReq *r : S->running) k = std::min(k, r->limit - r->sweeps);
+    k = std::max(k, 0);
+    for (int j = 0; j < k; ++j) {
+      Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
+      if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_run, S->d_wg_res, kBatchViGrid, s)) !=
+          hipSuccess)
+        return hip_fail(S->ctx, e, "serve sweep");
+      if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
+        return hip_fail(S->ctx, e, "serve close");
+    }
+    for (ServeReq *r : S->running) r->sweeps += k;
+    if ((e = launch_vi_status_batched(S->d_vrun, n_run, S->d_vstat, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve status");
+  }
+  std::vector<mdp_vi_stats> hv(n_run);
+  if (!fresh.empty() &&
+      (e = hipMemcpyAsync(hb.data(), d_bstats, sizeof(mdp_build_stats) * fresh.size(), hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+    return hip_fail(S->ctx, e, "serve build stats");
+  if (n_run > 0 &&
+      (e = hipMemcpyAsync(hv.data(), S->d_vstat, sizeof(mdp_vi_stats) * n_run, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+    return hip_fail(S->ctx, e, "serve vi stats");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(S->ctx, e, "serve sync");
+  give(S->alloc, bblk);
+  // ---- build results: shrink each model to its nonzeros
+  for (size_t i = 0; i < fresh.size(); ++i) {
+    ServeReq *r = fresh[i];
+    r->res.nnz = hb[i].nnz;
+    r->res.samples = hb[i].samples;
+    r->res.build_status = hb[i].status;
+    if (hb[i].status == MDP_OK) {
+      S->alloc.shrink(r->col.off, r->col.len, 4 * (size_t)hb[i].nnz);
+      S->alloc.shrink(r->cnt.off, r->cnt.len, 2 * (size_t)hb[i].nnz);
+      r->col.len = align_up(std::max<size_t>(4 * (size_t)hb[i].nnz, 1));
+      r->cnt.len = align_up(std::max<size_t>(2 * (size_t)hb[i].nnz, 1));
+      r->model_cap = hb[i].nnz;
+    }
+  }
+  // ---- retire converged requests (and failed builds)
+  std::vector<ServeReq *> ret, keep;
+  for (int i = 0; i < n_run; ++i) {
+    ServeReq *r = S->running[i];
+    r->res.sweeps = hv[i].sweeps;
+    r->res.residual = hv[i].residual;
+    const bool failed = r->res.build_status != MDP_OK;
+    if (failed || hv[i].status == MDP_OK || r->sweeps >= r->limit)
+      ret.push_back(r);
+    else
+      keep.push_back(r);
+  }
+  if (!ret.empty()) {
+    const int n = (int)ret.size();
+    if ((rc = upload_vi(S, ret, S->d_vret, S->d_bs_ret, s)) != MDP_OK) return rc;
+    if ((e = launch_vi_finish_batched(S->d_vret, n, S->d_vstat, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve finish");
+    {
+      Timed tm(S->ctx, MDP_KERNEL_POLICY, s);
+      if ((e = launch_policy_batched(S->d_vret, n, S->d_bs_ret, kBatchViGrid, s)) != hipSuccess)
+        return hip_fail(S->ctx, e, "serve policy");
+    }
+    std::vector<mdp_vi_stats> hf(n);
+    std::vector<double> vstart(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      ServeReq *r = ret[i];
+      const size_t ns = (size_t)r->z.ns;
+      const int64_t s0 = (int64_t)r->p.start_j * r->p.nx + r->p.start_i;
+      if ((e = hipMemcpyAsync(&vstart[i], r->v + s0, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (r->h_pi && (e = hipMemcpyAsync(r->h_pi, r->pi, 4 * ns, hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+          (r->h_v && (e = hipMemcpyAsync(r->h_v, r->v, 8 * ns, hipMemcpyDeviceToHost, s)) != hipSuccess))
+        return hip_fail(S->ctx, e, "serve results");
+    }
+    if ((e = hipMemcpyAsync(hf.data(), S->d_vstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve retire");
+    for (int i = 0; i < n; ++i) {
+      ServeReq *r = ret[i];
+      r->res.sweeps = hf[i].sweeps;
+      r->res.residual = hf[i].residual;
+      r->res.v_start = vstart[i];
+      r->res.status = r->res.build_status != MDP_OK ? r->res.build_status : hf[i].status;
+      r->res.done_step = S->step_no;
+      S->done.push_back(r->res);
+      unreserve(S, r);
+      delete r;
+    }
+  }
+  S->running.swap(keep);
+  if (n_active) *n_active = (int32_t)(S->queue.size() + S->running.size());
+  return MDP_OK;
+}
+
+mdp_status mdp_server_poll(mdp_server *S, mdp_served *out, int32_t max_out, int32_t *n_out)
+{
+  if (!S || !n_out || max_out < 0 || (max_out > 0 && !out)) return MDP_E_INVALID;
+  const int n = std::min<int>(max_out, (int)S->done.size());
+  for (int i = 0; i < n; ++i) out[i] = S->done[i];
+  S->done.erase(S->done.begin(), S->done.begin() + n);
+  *n_out = n;
+  return MDP_OK;
+}
+
+mdp_status mdp_server_info(mdp_server *S, mdp_server_state *out)
+{
+  if (!S || !out) return MDP_E_INVALID;
+  out->queued = (int32_t)S->queue.size();
+  out->in_flight = (int32_t)S->running.size();
+  out->completed = (int32_t)S->done.size();
+  out->pad = 0;
+  out->pool_used = (int64_t)S->alloc.used();
+  out->steps = S->step_no;
+  return MDP_OK;
+}
+
+mdp_status mdp_server_destroy(mdp_server *S)
+{
+  if (!S) return MDP_E_INVALID;
+  serve_free_all(S);
   return MDP_OK;
 }
 

@@ -98,10 +98,26 @@ __device__ inline uint64_t pack_entry(int32_t col, uint32_t cnt)
   return (uint64_t)(uint32_t)col | ((uint64_t)cnt << 32);
 }
 
-template <int KMAX, bool PACK16, bool NEAR>
-__global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const SlabParams S)
+// Where one tile's outputs go. row_nnz/row_off are indexed from row_base for
+// lane 0 of the tile; the staged entries go to `stage` when it is set, else to
+// a slot bump-allocated from `pool` (recorded in *base_out, -1 on overflow).
+struct TileOut {
+  uint32_t *row_nnz, *row_off;
+  int64_t row_base;
+  uint64_t *stage;
+  uint32_t *total_out;
+  uint64_t *pool;
+  unsigned long long *pool_top;
+  int64_t pool_cap;
+  int64_t *base_out;
+};
+
+// One tile of cells at layer t, every action of those cells, every realization.
+// POOL: entries go to a bump-allocated pool slot instead of O.stage.
+template <int KMAX, bool PACK16, bool NEAR, bool POOL>
+__device__ void build_tile(const BuildParams &P, const int t, const int tile, BuildState *bst,
+                           const TileOut &O, uint32_t *lds)
 {
-  extern __shared__ __align__(16) uint32_t lds[];
   const int HW = P.hw;                              // words per bin (power of 2)
   const int sstr = 2 * P.rch + 4;                   // floats per staged cell (padded)
   uint32_t *hist = lds;
@@ -110,13 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
   uint32_t *red = reinterpret_cast<uint32_t *>(tab + 2 * kMaxA);  // 16 words
 
   const int tid = threadIdx.x;
-  const int wg = blockIdx.x;
-  const int tl = wg / P.tiles_per_layer;
-  const int tile = wg - tl * P.tiles_per_layer;
-  const int t = S.t0 + tl;
   const int c0 = tile * P.cells_per_tile;
   const int ncell = min(P.cells_per_tile, P.nc - c0);
   const int nc = P.nc;
+  __syncthreads();  // LDS may still be read by the previous tile of a persistent loop
 
   // ---- this lane's row (cell cl of the tile, action a)
   const int cl = tid / P.na;
@@ -161,11 +174,17 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
     const int nloc = min(P.rch, P.nr - r0);
     // ---------------- phase A: lane = realization
     {
-      const int r = r0 + rlane;
       const bool rv = rlane < nloc;
+      const int r = rv ? r0 + rlane : r0;  // clamped: every load below is in bounds
+      // Coefficients beyond K are zero, so their fma(0, phi, u) terms return u
+      // exactly and the landing arithmetic is the K-term sum; loads are clamped
+      // to mode K-1 instead of branching per term.
       float m[KMAX];
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k) m[k] = (k < P.K && rv) ? mu_t[(size_t)k * P.nr + r] : 0.0f;
+      for (int k = 0; k < KMAX; ++k) {
+        const float val = mu_t[(size_t)min(k, P.K - 1) * P.nr + r];
+        m[k] = (k < P.K) ? val : 0.0f;
+      }
       for (int q = qg; q < ncell; q += nqg) {
         const int cq = c0 + q;
         const int qi = cq % P.nx, qj = cq / P.nx;
@@ -177,11 +196,11 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
         const float *pu = P.phiu + tp_off + cq;
         const float *pv = P.phiv + tp_off + cq;
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < P.K) {
-            u = __builtin_fmaf(m[k], pu[(size_t)k * nc], u);
-            v = __builtin_fmaf(m[k], pv[(size_t)k * nc], v);
-          }
+        for (int k = 0; k < KMAX; ++k) {
+          const size_t ko = (size_t)min(k, P.K - 1) * nc;
+          u = __builtin_fmaf(m[k], pu[ko], u);
+          v = __builtin_fmaf(m[k], pv[ko], v);
+        }
         float px = __builtin_fmaf(u, P.lam_x, (float)qi + 0.5f);
         float py = __builtin_fmaf(v, P.lam_y, (float)qj + 0.5f);
         if (rv && !(fabsf(u) <= P.usafe && fabsf(v) <= P.vsafe)) {
@@ -265,9 +284,9 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
     const unsigned long long nr_ = block_sum_u64(NEAR ? near_cnt : 0u, red64);
     const unsigned long long smp = block_sum_u64(sampled ? (unsigned long long)P.nr : 0ull, red64);
     if (tid == 0) {
-      if (e) atomicAdd(&S.st->n_escape, e);
-      if (nr_) atomicAdd(&S.st->n_near, nr_);
-      atomicAdd(&S.st->samples, smp);
+      if (e) atomicAdd(&bst->n_escape, e);
+      if (nr_) atomicAdd(&bst->n_near, nr_);
+      atomicAdd(&bst->samples, smp);
     }
   }
 
@@ -347,16 +366,29 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
   // ---------------- workgroup offsets
   uint32_t total;
   const uint32_t off = block_excl_scan(nnz, red, total);
-  const int64_t srow = (((int64_t)t * nc + c0) * P.na + tid) - S.row0;
   if (lane_row) {
-    S.row_nnz[srow] = nnz;
-    S.row_off[srow] = off;
+    O.row_nnz[O.row_base + tid] = nnz;
+    O.row_off[O.row_base + tid] = off;
   }
-  if (tid == 0) S.wg_nnz[wg] = total;
+  if (tid == 0) *O.total_out = total;
+  // Staging block: fixed per tile, or bump-allocated from the pool (a tile
+  // that does not fit is recorded as -1 and writes nothing).
+  uint64_t *blk = O.stage;
+  if constexpr (POOL) {
+    unsigned long long *bcast = reinterpret_cast<unsigned long long *>(red) + 2;
+    if (tid == 0) {
+      const unsigned long long b0 = atomicAdd(O.pool_top, (unsigned long long)total);
+      const bool fits = (int64_t)(b0 + total) <= O.pool_cap;
+      *O.base_out = fits ? (int64_t)b0 : -1;
+      bcast[0] = fits ? b0 : ~0ull;
+    }
+    __syncthreads();
+    blk = (bcast[0] != ~0ull) ? O.pool + bcast[0] : nullptr;
+  }
 
   // ---------------- compaction, pass 2: write the row's entries
-  if (lane_row) {
-    uint64_t *out = S.stage + (int64_t)wg * S.wg_cap + off;
+  if (lane_row && blk != nullptr) {
+    uint64_t *out = blk + off;
     if (!sampled) {
       out[0] = pack_entry(is_target ? TARGET : DEAD, (uint32_t)P.nr);
     } else {
@@ -380,6 +412,27 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
       if (tgt) out[k++] = pack_entry(TARGET, tgt);
     }
   }
+}
+
+template <int KMAX, bool PACK16, bool NEAR>
+__global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const SlabParams S)
+{
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int wg = blockIdx.x;
+  const int tl = wg / P.tiles_per_layer;
+  const int tile = wg - tl * P.tiles_per_layer;
+  const int t = S.t0 + tl;
+  TileOut O;
+  O.row_nnz = S.row_nnz;
+  O.row_off = S.row_off;
+  O.row_base = ((int64_t)t * P.nc + (int64_t)tile * P.cells_per_tile) * P.na - S.row0;
+  O.stage = S.stage + (int64_t)wg * S.wg_cap;
+  O.total_out = S.wg_nnz + wg;
+  O.pool = nullptr;
+  O.pool_top = nullptr;
+  O.pool_cap = 0;
+  O.base_out = nullptr;
+  build_tile<KMAX, PACK16, NEAR, false>(P, t, tile, S.st, O, lds);
 }
 
 // Action displacement tables into device memory (one thread per entry).
@@ -550,6 +603,140 @@ __global__ __launch_bounds__(kBlock) void k_max_speed(const BuildParams P, unsig
   }
 }
 
+// ------------------------------------------------------------------ batches
+__global__ void k_batch_build_init(BatchBuildDesc *D, int n, unsigned int *counter,
+                                   unsigned long long *pool_top)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *counter = 0u;
+    *pool_top = 0ull;
+  }
+  if (i < n) {
+    BuildState *st = D[i].st;
+    st->n_escape = 0;
+    st->n_near = 0;
+    st->samples = 0;
+    st->running_nnz = 0;
+    st->pad[0] = 0;  // pool overflow flag
+  }
+}
+
+// Persistent build over every problem of a batch: workgroups take (problem,
+// layer, tile) items from a shared counter until the list (sorted by cost,
+// largest first) runs out; each item's entries go to a bump-allocated pool slot.
+template <int KMAX, bool NEAR>
+__global__ __launch_bounds__(kBlock) void k_build_batched(const BatchBuildDesc *D, const BatchItem *items,
+                                                           int n_items, unsigned int *counter, uint64_t *pool,
+                                                           unsigned long long *pool_top, int64_t pool_cap)
+{
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = item_s;
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem w = items[it];
+    const BatchBuildDesc &d = D[w.inst];
+    const int64_t local = (int64_t)w.t * d.P.tiles_per_layer + w.tile;
+    TileOut O;
+    O.row_nnz = d.row_nnz;
+    O.row_off = d.row_off;
+    O.row_base = ((int64_t)w.t * d.P.nc + (int64_t)w.tile * d.P.cells_per_tile) * d.P.na;
+    O.stage = nullptr;
+    O.total_out = d.item_total + local;
+    O.pool = pool;
+    O.pool_top = pool_top;
+    O.pool_cap = pool_cap;
+    O.base_out = d.item_base + local;
+    build_tile<KMAX, true, NEAR, true>(d.P, w.t, w.tile, d.st, O, lds);
+  }
+}
+
+// Per problem (one block each): exclusive scan of its items' entry counts in
+// row order, the end of row_ptr, the nnz total and the pool-overflow flag.
+__global__ __launch_bounds__(1024) void k_batch_scan(BatchBuildDesc *D)
+{
+  BatchBuildDesc &d = D[blockIdx.x];
+  __shared__ long long sh[1024];
+  const int tid = threadIdx.x;
+  const int64_t n = d.n_items;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = min(n, (int64_t)tid * per), hi = min(n, lo + per);
+  long long s = 0;
+  int over = 0;
+  for (int64_t k = lo; k < hi; ++k) {
+    s += d.item_total[k];
+    over |= (d.item_base[k] < 0) ? 1 : 0;
+  }
+  over = __syncthreads_or(over);
+  sh[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long long y = (tid >= o) ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += y;
+    __syncthreads();
+  }
+  long long acc = sh[tid] - s;
+  for (int64_t k = lo; k < hi; ++k) {
+    d.item_off[k] = acc;
+    acc += d.item_total[k];
+  }
+  if (tid == 1023) {
+    d.st->running_nnz = sh[1023];
+    d.M.row_ptr[d.P.rows] = sh[1023];
+    d.st->pad[0] = over;
+  }
+}
+
+// Every item: row_ptr of its rows and its pool slot into the CSR (capacity-checked).
+__global__ __launch_bounds__(kBlock) void k_batch_copy(const BatchBuildDesc *D, const BatchItem *items,
+                                                        int n_items, const uint64_t *pool)
+{
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const BatchItem w = items[it];
+    const BatchBuildDesc &d = D[w.inst];
+    const int64_t local = (int64_t)w.t * d.P.tiles_per_layer + w.tile;
+    const int c0 = w.tile * d.P.cells_per_tile;
+    const int ncell = min(d.P.cells_per_tile, d.P.nc - c0);
+    const int64_t row0 = ((int64_t)w.t * d.P.nc + c0) * d.P.na;
+    const int64_t off = d.item_off[local];
+    const int64_t base = d.item_base[local];
+    const uint32_t n = d.item_total[local];
+    if (tid < ncell * d.P.na) d.M.row_ptr[row0 + tid] = off + d.row_off[row0 + tid];
+    if (base >= 0) {
+      for (uint32_t k = tid; k < n; k += kBlock) {
+        const int64_t dst = off + k;
+        if (dst < d.M.capacity) {
+          const uint64_t e = pool[base + k];
+          d.M.col[dst] = (int32_t)(uint32_t)e;
+          d.M.cnt[dst] = (uint16_t)(e >> 32);
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_batch_finalize(BatchBuildDesc *D, int n, mdp_build_stats *out)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BuildState *st = D[i].st;
+  mdp_build_stats o;
+  o.samples = (int64_t)st->samples;
+  o.nnz = st->running_nnz;
+  o.n_escape = (int64_t)st->n_escape;
+  o.n_near_edge = D[i].near_asked ? (int64_t)st->n_near : -1;
+  o.status = o.n_escape ? MDP_E_SUBGRID
+                        : (st->pad[0] ? MDP_E_SCRATCH : (o.nnz > D[i].M.capacity ? MDP_E_CAPACITY : MDP_OK));
+  o.n_slabs = 1;
+  out[i] = o;
+}
+
 // ------------------------------------------------------------------ launchers
 hipError_t launch_fill_tab(const ActionTables &T, float *tab, hipStream_t s)
 {
@@ -594,8 +781,74 @@ hipError_t launch_build_slab(const BuildParams &P, const SlabParams &S, int kmax
   switch (kmax) {
     case 4: return launch_build_k<4>(P, S, pack16, near, lds, s);
     case 8: return launch_build_k<8>(P, S, pack16, near, lds, s);
+    case 12: return launch_build_k<12>(P, S, pack16, near, lds, s);
     default: return launch_build_k<16>(P, S, pack16, near, lds, s);
   }
+}
+
+hipError_t launch_batch_build_init(BatchBuildDesc *D, int n, unsigned int *counter,
+                                   unsigned long long *pool_top, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_batch_build_init, dim3((n + 255) / 256), dim3(256), 0, s, D, n, counter, pool_top);
+  return hipGetLastError();
+}
+
+template <int KMAX, bool NEAR>
+static const void *batch_kernel()
+{
+  return (const void *)k_build_batched<KMAX, NEAR>;
+}
+
+static const void *batch_kernel_for(int kmax, bool near)
+{
+  switch (kmax) {
+    case 4: return near ? batch_kernel<4, true>() : batch_kernel<4, false>();
+    case 8: return near ? batch_kernel<8, true>() : batch_kernel<8, false>();
+    case 12: return near ? batch_kernel<12, true>() : batch_kernel<12, false>();
+    default: return near ? batch_kernel<16, true>() : batch_kernel<16, false>();
+  }
+}
+
+hipError_t batch_build_occupancy(int kmax, bool near, size_t lds, int *blocks_per_cu)
+{
+  const void *k = batch_kernel_for(kmax, near);
+  // the persistent kernel also holds a little static LDS (its current item)
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, k);
+  if (e != hipSuccess) return e;
+  const size_t limit = 160 * 1024 - fa.sharedSizeBytes;
+  if (lds > limit) return hipErrorInvalidValue;
+  if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit)) != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kBlock, lds);
+}
+
+hipError_t launch_batch_build(const BatchBuildDesc *D, const BatchItem *items, int n_items, unsigned int *counter,
+                              uint64_t *pool, unsigned long long *pool_top, int64_t pool_cap, int kmax, bool near,
+                              size_t lds, int grid, hipStream_t s)
+{
+  void *args[] = {(void *)&D, (void *)&items, (void *)&n_items, (void *)&counter,
+                  (void *)&pool, (void *)&pool_top, (void *)&pool_cap};
+  return hipLaunchKernel(batch_kernel_for(kmax, near), dim3(grid), dim3(kBlock), args, lds, s);
+}
+
+hipError_t launch_batch_scan(BatchBuildDesc *D, int n, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_batch_scan, dim3(n), dim3(1024), 0, s, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_copy(const BatchBuildDesc *D, const BatchItem *items, int n_items, const uint64_t *pool,
+                             hipStream_t s)
+{
+  const int grid = n_items < 8192 ? n_items : 8192;
+  hipLaunchKernelGGL(k_batch_copy, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, s, D, items, n_items, pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(BatchBuildDesc *D, int n, mdp_build_stats *out, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_batch_finalize, dim3((n + 63) / 64), dim3(64), 0, s, D, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_scan_wg(const SlabParams &S, int n_wg, int64_t *row_ptr_end, hipStream_t s)

@@ -48,6 +48,13 @@ struct ActionTables {
   float hx[kMaxA], hy[kMaxA];
 };
 
+struct ModelOut {
+  int64_t *row_ptr;
+  int32_t *col;
+  uint16_t *cnt;
+  int64_t capacity;
+};
+
 // Per-pass parameters: one pass covers decision layers [t0, t0 + nlayers).
 struct SlabParams {
   int t0, nlayers;
@@ -61,11 +68,24 @@ struct SlabParams {
   BuildState *st;
 };
 
-struct ModelOut {
-  int64_t *row_ptr;
-  int32_t *col;
-  uint16_t *cnt;
-  int64_t capacity;
+// One problem of a batch (device-resident descriptor, see batch launchers).
+struct BatchBuildDesc {
+  BuildParams P;             // P.tab points at this problem's action tables
+  BuildState *st;            // this problem's bookkeeping
+  uint32_t *row_nnz;         // [rows]
+  uint32_t *row_off;         // [rows] offset of the row inside its tile's block
+  uint32_t *item_total;      // [n_items] entries of tile item (layer, tile)
+  int64_t *item_base;        // [n_items] pool slot of the item (-1: did not fit)
+  int64_t *item_off;         // [n_items] global CSR offset of the item
+  ModelOut M;
+  int64_t n_items;           // nt * tiles_per_layer
+  int near_asked;
+  int pad;
+};
+
+// Work item of the persistent batched build: problem, layer, tile.
+struct BatchItem {
+  int inst, t, tile, pad;
 };
 
 // Launchers (return hipError_t of the launch)
@@ -79,6 +99,16 @@ hipError_t launch_copy(const BuildParams &P, const SlabParams &S, const ModelOut
 hipError_t launch_build_finalize(BuildState *st, int64_t capacity, int n_slabs, int near_asked,
                                  hipStream_t s);
 hipError_t launch_escape_only(const BuildParams &P, BuildState *st, hipStream_t s);
+hipError_t launch_batch_build_init(BatchBuildDesc *D, int n, unsigned int *counter,
+                                   unsigned long long *pool_top, hipStream_t s);
+hipError_t launch_batch_build(const BatchBuildDesc *D, const BatchItem *items, int n_items,
+                              unsigned int *counter, uint64_t *pool, unsigned long long *pool_top,
+                              int64_t pool_cap, int kmax, bool near, size_t lds, int grid, hipStream_t s);
+hipError_t batch_build_occupancy(int kmax, bool near, size_t lds, int *blocks_per_cu);
+hipError_t launch_batch_scan(BatchBuildDesc *D, int n, hipStream_t s);
+hipError_t launch_batch_copy(const BatchBuildDesc *D, const BatchItem *items, int n_items, const uint64_t *pool,
+                             hipStream_t s);
+hipError_t launch_batch_finalize(BatchBuildDesc *D, int n, mdp_build_stats *out, hipStream_t s);
 hipError_t launch_max_speed(const BuildParams &P, unsigned int *umax_bits, hipStream_t s);
 
 // Value iteration / policy
@@ -99,15 +129,33 @@ struct VIParams {
   const float *R;           // reward block of the mission
   int64_t cap;              // length of col / cnt
   int64_t ns;
-  int na, states_per_wg, n_wg;   // n_wg: launched workgroups (grid-stride)
+  int na, states_per_wg, n_wg;   // states per block (2 rows per thread); launched workgroups
   int64_t n_blocks;              // blocks of states_per_wg states
   double inv_nr, tol;
   VIState *st;
 };
 
-hipError_t launch_vi_init(VIState *st, hipStream_t s);
-hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, int parity,
-                           hipStream_t s);
+// One problem of a batched solve (device-resident descriptor).
+struct BatchVIDesc {
+  VIParams P;         // P.st points at this problem's sweep state
+  VIState *st;
+  double *v, *v_alt;  // values (caller) and the second buffer (scratch)
+  int32_t *pi;        // policy (caller)
+  int64_t pad;
+};
+
+constexpr int kMaxBatch = 1024;  // problems per batch
+
+hipError_t launch_vi_init(VIState *st, int n, hipStream_t s);
+hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, hipStream_t s);
+hipError_t launch_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *block_start, double *wg_res,
+                                   int grid, hipStream_t s);
+hipError_t launch_vi_reset_batched(const BatchVIDesc *D, int n, hipStream_t s);
+hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s);
+hipError_t launch_vi_close_batched(const BatchVIDesc *D, int n, int grid, const double *wg_res, double tol,
+                                   hipStream_t s);
+hipError_t launch_vi_finish_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s);
+hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *block_start, int grid, hipStream_t s);
 hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, mdp_vi_stats *dev_stats,
                             hipStream_t s);
 hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s);

@@ -75,6 +75,22 @@ class MdpViStats(C.Structure):
 _lib = None
 
 
+class MdpServerConfig(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("sweeps_per_step", C.c_int32), ("max_sweeps", C.c_int32),
+                ("pad", C.c_int32), ("tol", C.c_double)]
+
+
+class MdpServed(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("nnz", C.c_int64), ("samples", C.c_int64), ("admit_step", C.c_int64),
+                ("done_step", C.c_int64), ("residual", C.c_double), ("v_start", C.c_double),
+                ("status", C.c_int32), ("build_status", C.c_int32), ("sweeps", C.c_int32), ("pad", C.c_int32)]
+
+
+class MdpServerState(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("in_flight", C.c_int32), ("completed", C.c_int32), ("pad", C.c_int32),
+                ("pool_used", C.c_int64), ("steps", C.c_int64)]
+
+
 def load():
     """Load libmdp.so; raise if it has not been built (there is no fallback)."""
     global _lib
@@ -95,6 +111,22 @@ def load():
             "mdp_value_iterate": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp,
                                    C.c_size_t, vp, vp], C.c_int32),
             "mdp_policy": ([vp, P, C.POINTER(MdpModel), C.c_int32, vp, vp, vp], C.c_int32),
+            "mdp_batch_query": ([C.c_int32, P, C.c_int64, C.POINTER(C.c_size_t)], C.c_int32),
+            "mdp_batch_create": ([vp, C.c_int32, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), vp, vp, vp, C.c_int64,
+                                  vp, C.c_size_t, C.POINTER(vp)], C.c_int32),
+            "mdp_batch_build": ([vp, vp], C.c_int32),
+            "mdp_batch_solve": ([vp, C.c_double, C.c_int32, vp], C.c_int32),
+            "mdp_batch_stats": ([vp, vp, vp], C.c_int32),
+            "mdp_batch_capture": ([vp, C.c_double, C.c_int32, vp], C.c_int32),
+            "mdp_batch_replay": ([vp, vp], C.c_int32),
+            "mdp_batch_destroy": ([vp], C.c_int32),
+            "mdp_server_footprint": ([P, C.POINTER(C.c_size_t)], C.c_int32),
+            "mdp_server_create": ([vp, C.POINTER(MdpServerConfig), vp, C.c_size_t, C.POINTER(vp)], C.c_int32),
+            "mdp_server_submit": ([vp, P, C.POINTER(MdpEnv), C.c_int32, vp, vp, C.c_int64], C.c_int32),
+            "mdp_server_step": ([vp, vp, C.POINTER(C.c_int32)], C.c_int32),
+            "mdp_server_poll": ([vp, C.POINTER(MdpServed), C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
+            "mdp_server_info": ([vp, C.POINTER(MdpServerState)], C.c_int32),
+            "mdp_server_destroy": ([vp], C.c_int32),
             "mdp_ctx_profile": ([vp, C.c_int32], C.c_int32),
             "mdp_ctx_profile_read": ([vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int32),
         }
@@ -108,7 +140,10 @@ def load():
 
 EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_error", "mdp_build_query",
             "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_policy", "mdp_ctx_profile",
-            "mdp_ctx_profile_read"]
+            "mdp_ctx_profile_read", "mdp_batch_query", "mdp_batch_create", "mdp_batch_build", "mdp_batch_solve",
+            "mdp_batch_stats", "mdp_batch_capture", "mdp_batch_replay", "mdp_batch_destroy",
+            "mdp_server_footprint", "mdp_server_create", "mdp_server_submit", "mdp_server_step",
+            "mdp_server_poll", "mdp_server_info", "mdp_server_destroy"]
 MDP_KERNEL_BUILD, MDP_KERNEL_VI_SWEEP, MDP_KERNEL_POLICY, MDP_KERNEL_COPY = 0, 1, 2, 3
 
 
@@ -297,3 +332,183 @@ class Planner:
         pi = torch.empty(ns, dtype=torch.int32, device=self.device)
         mdp_policy(self.ctx, problem, model, mission, v, pi, stream)
         return pi
+
+
+# ---------------------------------------------------------------- batches
+def _model_struct(m: dict) -> MdpModel:
+    return MdpModel(_ptr(m["row_ptr"]), _ptr(m["col"]), _ptr(m["cnt"]), _ptr(m["reward"]), int(m["col"].numel()))
+
+
+def mdp_batch_query(problems: list, pool_entries: int = 0) -> int:
+    arr = (MdpProblem * len(problems))(*[problem_struct(p) for p in problems])
+    out = C.c_size_t()
+    rc = load().mdp_batch_query(len(problems), arr, pool_entries, C.byref(out))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_batch_query: invalid batch")
+    return out.value
+
+
+class Batch:
+    """Many problems built in one persistent launch and solved with one sweep
+    launch per iteration (include/mdp.h, mdp_batch_*). Allocates models,
+    values, policies and scratch with torch; recreates itself once if a model
+    or the staging pool was too small."""
+
+    def __init__(self, planner: "Planner", problems: list, envs: list, missions: list, pool_entries: int = 0,
+                 capacities: list | None = None):
+        self.pl, self.problems, self.envs, self.missions = planner, problems, envs, list(missions)
+        self.n = len(problems)
+        self.h = None
+        sizes = [mdp_build_query(p) for p in problems]
+        caps = capacities or [min(s["nnz_upper"], 4 * s["n_rows"] + 1024) for s in sizes]
+        self._create(caps, pool_entries)
+
+    def _create(self, caps, pool_entries):
+        d = self.pl.device
+        self.models = [self.pl.alloc_model(p, c) for p, c in zip(self.problems, caps)]
+        sizes = [mdp_build_query(p) for p in self.problems]
+        self.v = [torch.zeros(s["n_states"], dtype=torch.float64, device=d) for s in sizes]
+        self.pi = [torch.zeros(s["n_states"], dtype=torch.int32, device=d) for s in sizes]
+        self.pool_entries = pool_entries
+        nbytes = mdp_batch_query(self.problems, pool_entries)
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=d)
+        n = self.n
+        probs = (MdpProblem * n)(*[problem_struct(p) for p in self.problems])
+        envs = (MdpEnv * n)(*[MdpEnv(*[_ptr(e.get(k)) for k, _ in MdpEnv._fields_]) for e in self.envs])
+        mods = (MdpModel * n)(*[_model_struct(m) for m in self.models])
+        miss = (C.c_int32 * n)(*self.missions)
+        vptr = (C.c_void_p * n)(*[t.data_ptr() for t in self.v])
+        pptr = (C.c_void_p * n)(*[t.data_ptr() for t in self.pi])
+        h = C.c_void_p()
+        rc = load().mdp_batch_create(self.pl.ctx, n, probs, envs, mods, miss, vptr, pptr, pool_entries,
+                                     self.scratch.data_ptr(), self.scratch.numel(), C.byref(h))
+        _check(self.pl.ctx, rc, "mdp_batch_create")
+        self.h = h
+
+    def build(self, stream=None):
+        _check(self.pl.ctx, load().mdp_batch_build(self.h, _stream_handle(stream)), "mdp_batch_build")
+
+    def solve(self, tol: float = 1e-6, max_sweeps: int = 100000, stream=None):
+        _check(self.pl.ctx, load().mdp_batch_solve(self.h, tol, max_sweeps, _stream_handle(stream)),
+               "mdp_batch_solve")
+
+    def capture(self, tol: float = 1e-6, max_sweeps: int = 100000, stream=None):
+        _check(self.pl.ctx, load().mdp_batch_capture(self.h, tol, max_sweeps, _stream_handle(stream)),
+               "mdp_batch_capture")
+
+    def replay(self, stream=None):
+        _check(self.pl.ctx, load().mdp_batch_replay(self.h, _stream_handle(stream)), "mdp_batch_replay")
+
+    def stats(self):
+        """Per-problem build and solve stats (call after the stream has finished)."""
+        b = (MdpBuildStats * self.n)()
+        v = (MdpViStats * self.n)()
+        _check(self.pl.ctx, load().mdp_batch_stats(self.h, b, v), "mdp_batch_stats")
+        conv = lambda s, cls: {k: getattr(s, k) for k, _ in cls._fields_}
+        return [conv(x, MdpBuildStats) for x in b], [conv(x, MdpViStats) for x in v]
+
+    def build_checked(self, stream=None):
+        """Build; if a model or the staging pool was too small, recreate with exact sizes and
+        build again. Returns the per-problem build stats."""
+        for _ in range(2):
+            self.build(stream)
+            (stream or torch.cuda.current_stream()).synchronize()
+            bs, _ = self.stats()
+            statuses = {s["status"] for s in bs}
+            if statuses <= {MDP_OK}:
+                return bs
+            if statuses - {MDP_OK, MDP_E_CAPACITY, MDP_E_SCRATCH}:
+                return bs
+            caps = [max(s["nnz"], m["col"].numel()) for s, m in zip(bs, self.models)]
+            pool = sum(s["nnz"] for s in bs) + 1024
+            self.close()
+            self._create(caps, max(pool, self.pool_entries))
+        return bs
+
+    def close(self):
+        if self.h is not None:
+            load().mdp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mdp_server_footprint(problem: dict) -> int:
+    n = C.c_size_t()
+    rc = load().mdp_server_footprint(C.byref(problem_struct(problem)), C.byref(n))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_server_footprint")
+    return n.value
+
+
+class Server:
+    """Continuous-batching planner (include/mdp.h, mdp_server_*): requests are
+    queued with submit(), each step() admits, builds, sweeps and retires, and
+    poll() returns completion records. The model pool is one torch allocation;
+    each request's policy (and optionally values) is copied into pinned host
+    tensors owned here until its completion is polled."""
+
+    def __init__(self, planner: "Planner", pool_bytes: int, max_inflight: int = 64, sweeps_per_step: int = 8,
+                 tol: float = 1e-6, max_sweeps: int = 100000, stream=None):
+        self.pl = planner
+        self.h = None
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=planner.device)
+        cfg = MdpServerConfig(max_inflight, sweeps_per_step, max_sweeps, 0, tol)
+        h = C.c_void_p()
+        _check(planner.ctx, load().mdp_server_create(planner.ctx, C.byref(cfg), self.pool.data_ptr(),
+                                                      self.pool.numel(), C.byref(h)), "mdp_server_create")
+        self.h = h
+        self.stream = stream
+        self.pending = {}  # tag -> (problem, env, pi, v) kept alive until polled
+
+    def submit(self, tag: int, problem: dict, env: dict, mission: int, keep_values: bool = False):
+        ns = problem["nt"] * problem["nx"] * problem["ny"]
+        pi = torch.empty(ns, dtype=torch.int32, pin_memory=True)
+        v = torch.empty(ns, dtype=torch.float64, pin_memory=True) if keep_values else None
+        ps = problem_struct(problem)
+        es = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
+        rc = load().mdp_server_submit(self.h, C.byref(ps), C.byref(es), mission, pi.data_ptr(),
+                                      v.data_ptr() if v is not None else None, tag)
+        _check(self.pl.ctx, rc, "mdp_server_submit")
+        self.pending[tag] = (problem, env, pi, v)
+
+    def step(self) -> int:
+        n = C.c_int32()
+        _check(self.pl.ctx, load().mdp_server_step(self.h, _stream_handle(self.stream), C.byref(n)),
+               "mdp_server_step")
+        return n.value
+
+    def poll(self) -> list:
+        """Completion records as dicts, with the policy ("pi") and values ("v") tensors."""
+        out = []
+        buf = (MdpServed * 64)()
+        while True:
+            n = C.c_int32()
+            _check(self.pl.ctx, load().mdp_server_poll(self.h, buf, 64, C.byref(n)), "mdp_server_poll")
+            for k in range(n.value):
+                rec = {f: getattr(buf[k], f) for f, _ in MdpServed._fields_ if f != "pad"}
+                _, _, pi, v = self.pending.pop(rec["tag"])
+                rec["pi"], rec["v"] = pi, v
+                out.append(rec)
+            if n.value < 64:
+                return out
+
+    def info(self) -> dict:
+        st = MdpServerState()
+        _check(self.pl.ctx, load().mdp_server_info(self.h, C.byref(st)), "mdp_server_info")
+        return {f: getattr(st, f) for f, _ in MdpServerState._fields_ if f != "pad"}
+
+    def close(self):
+        if self.h is not None:
+            load().mdp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
