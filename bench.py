@@ -79,6 +79,8 @@ def batched_leg(pl, n_inst: int = 64, reps: int = 2) -> dict:
     t_gen = time.perf_counter() - t_gen
     missions = [w.missions()[0] for w in ws]
     envs = [pl.upload_env(w) for w in ws]
+    for w, env in zip(ws, envs):  # sub-grid sized from the synthesised velocities (untimed)
+        w.problem["sub_hx"], w.problem["sub_hy"] = mdp.mdp_subgrid_auto(pl.ctx, w.problem, env)
     samples = sum(w.nominal_samples for w in ws)
     b = mdp.Batch(pl, [w.problem for w in ws], envs, missions)
     bs = b.build_checked()
@@ -167,6 +169,9 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
     t_gen = time.perf_counter()
     arr, reqs = _served_trace(seconds, rate)
     envs = [pl.upload_env(w) for w, _ in reqs]
+    for (w, _), env in zip(reqs, envs):  # requests arrive with their sub-grid sized
+        if w.problem["sub_hx"] == 0 and w.problem["sub_hy"] == 0:
+            w.problem["sub_hx"], w.problem["sub_hy"] = mdp.mdp_subgrid_auto(pl.ctx, w.problem, env)
     t_gen = time.perf_counter() - t_gen
     n = len(reqs)
     samples = sum(w.nominal_samples for w, _ in reqs)
@@ -249,7 +254,19 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-trace leg")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the served trace")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrival rate (per second)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the planner has no multi-GPU path",
               file=sys.stderr)
@@ -320,10 +337,21 @@ def main():
     build_s = ms_b / 1e3 / builds           # all passes of one build
     build_launch_s = ms_b / 1e3 / n_b       # one launch
     ach_alu = build_ops / bs["n_slabs"] / build_launch_s
-    # VI sweep: compulsory bytes of the stored format per sweep.
-    sweep_bytes = 8 * (rows + 1) + 4 * rows + 6 * nnz + 8 * nst + 8 * nst
+    # VI: compulsory bytes of the stored format for the layers each sweep
+    # recomputes (sweep k of a solve recomputes layers t < nt - k + 1): per
+    # layer 8 B row pointer + 4 B reward per row, 6 B per nonzero, v read and
+    # written once per state.
+    nt, nc = p["nt"], p["nx"] * p["ny"]
+    rp_layer = model["row_ptr"][:: nc * na].cpu().numpy()  # row_ptr at layer starts (+ end)
+    nnz_layer = rp_layer[1:] - rp_layer[:-1]
+    layer_bytes = 12 * nc * na + 6 * nnz_layer + 16 * nc
+    solve_bytes = 0
+    for v in vst:
+        for k in range(v["sweeps"]):
+            solve_bytes += int(layer_bytes[: max(0, min(nt, nt - k + 1))].sum())
+    sweep_bytes = int(layer_bytes.sum()) + 8  # one full sweep
     sweep_s = ms_v / 1e3 / n_v
-    ach_hbm = sweep_bytes / sweep_s
+    ach_hbm = solve_bytes * args.steps / (ms_v / 1e3)
     sweeps_per_step = sum(v["sweeps"] for v in vst)
 
     roof_build = dict(bound="alu", achieved=ach_alu / 1e12, peak=VALU_LANE_OPS / 1e12, unit="Top/s",
@@ -335,7 +363,7 @@ def main():
     roof_build["fp32_flops_frac"] = flops / build_launch_s / FP32_VECTOR
     roof_vi = dict(bound="hbm", achieved=ach_hbm / 1e9, peak=HBM_BW / 1e9, unit="GB/s",
                    frac=ach_hbm / HBM_BW, traffic=None, kernel="k_vi_sweep",
-                   bytes_per_sweep=sweep_bytes, launch_ms=sweep_s * 1e3)
+                   bytes_full_sweep=sweep_bytes, bytes_per_step=solve_bytes, launch_ms=sweep_s * 1e3)
     dominant = roof_build if ms_b >= ms_v else roof_vi
 
     out = {

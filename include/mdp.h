@@ -202,7 +202,7 @@ mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model
  *     sweep count), then the greedy policy of each problem.
  * Every problem's model, values and policy equal those of mdp_build /
  * mdp_value_iterate / mdp_policy on it alone, bit for bit.
- * Ownership: models, values (fp64 [N_s], v0 = 0 is written by the solve),
+ * Ownership: models, values (fp64 [N_s]; every solve starts from v0 = 0),
  * policies and scratch are caller-owned device buffers; the batch owns only its
  * descriptor table. Device-side errors appear in mdp_batch_stats:
  * MDP_E_CAPACITY (model too small), MDP_E_SCRATCH (staging pool too small),

@@ -31,6 +31,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kStageBudget = size_t(4) << 30;  // staging bytes per build pass
+constexpr int kViGridMaxHost = 8192;  // most workgroups of one sweep launch
 constexpr size_t kLdsLimit = 160 * 1024 - 256;  // leaves room for a kernel's static LDS
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -133,7 +134,8 @@ const char *make_plan(const mdp_problem *p, Plan &pl)
   off = align_up(off + slab_wgs * (size_t)pl.wg_cap * 8);
   pl.build_bytes = off;
   const int64_t ns = (int64_t)p->nt * pl.nc;
-  pl.vi_bytes = align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)) + align_up((size_t)ns * 8);
+  pl.vi_bytes = align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)) + align_up((size_t)ns * 8) +
+                align_up(sizeof(double) * kViGridMaxHost);
   return nullptr;
 }
 
@@ -510,6 +512,34 @@ mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, con
   return MDP_OK;
 }
 
+// Sweep parameters of mission `mission` of a built model.
+static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const Plan &pl, int mission, int n_wg,
+                           VIParams &V)
+{
+  int slot = 0;
+  for (int m = 0; m < mission; ++m) slot += (int)(p->mission_mask >> m & 1u);
+  memset(&V, 0, sizeof(V));
+  V.row_ptr = model->row_ptr;
+  V.col = model->col;
+  V.cnt = model->cnt;
+  V.R = model->reward + (int64_t)slot * pl.rows;
+  V.cap = model->nnz_capacity;
+  V.ns = (int64_t)p->nt * pl.nc;
+  V.na = pl.na;
+  V.nx = p->nx;
+  V.ny = p->ny;
+  V.nc = pl.nc;
+  V.nt = p->nt;
+  V.hy = p->sub_hy;
+  V.states_per_wg = std::min(kViRows / pl.na, pl.nc);
+  V.blocks_per_layer = (pl.nc + V.states_per_wg - 1) / V.states_per_wg;
+  V.n_blocks = (int64_t)p->nt * V.blocks_per_layer;
+  V.win_rows = vi_window_rows(p->nx, p->ny, p->sub_hy, V.states_per_wg);
+  V.max_row = std::min(pl.nsg, p->n_real);
+  V.n_wg = n_wg;
+  V.inv_nr = 1.0 / (double)p->n_real;
+}
+
 static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
                            Plan &pl, VIParams &V)
 {
@@ -527,20 +557,7 @@ static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *
     set_err(ctx, "model buffers must be device pointers");
     return MDP_E_INVALID;
   }
-  int slot = 0;
-  for (int m = 0; m < mission; ++m) slot += (int)(p->mission_mask >> m & 1u);
-  memset(&V, 0, sizeof(V));
-  V.row_ptr = model->row_ptr;
-  V.col = model->col;
-  V.cnt = model->cnt;
-  V.R = model->reward + (int64_t)slot * pl.rows;
-  V.cap = model->nnz_capacity;
-  V.ns = (int64_t)p->nt * pl.nc;
-  V.na = pl.na;
-  V.states_per_wg = 2 * kBlock / pl.na;
-  V.n_blocks = (V.ns + V.states_per_wg - 1) / V.states_per_wg;
-  V.n_wg = (int)std::min<int64_t>(V.n_blocks, 2048);
-  V.inv_nr = 1.0 / (double)p->n_real;
+  fill_vi_params(p, model, pl, mission, kViGridMaxHost, V);
   return MDP_OK;
 }
 
@@ -564,6 +581,7 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   V.st = (VIState *)sc;
   mdp_vi_stats *dstats = (mdp_vi_stats *)(sc + align_up(sizeof(VIState)));
   double *v_alt = (double *)(sc + align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)));
+  double *wg_res = (double *)((char *)v_alt + align_up((size_t)V.ns * 8));
   V.tol = tol;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
@@ -576,7 +594,8 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
     const double *vin = (k & 1) ? v_alt : d_v;
     double *vout = (k & 1) ? d_v : v_alt;
     Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
-    if ((e = launch_vi_sweep(V, vin, vout, s)) != hipSuccess) return hip_fail(ctx, e, "vi sweep");
+    if ((e = launch_vi_sweep(V, vin, vout, vi_active_layers(p->nt, k), wg_res, s)) != hipSuccess)
+      return hip_fail(ctx, e, "vi sweep");
   }
   if ((e = launch_vi_finish(V, d_v, v_alt, dstats, s)) != hipSuccess) return hip_fail(ctx, e, "vi finish");
   if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_vi_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -606,7 +625,7 @@ mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model
 // ====================================================================== batches
 namespace {
 
-constexpr int kBatchViGrid = 2048;
+constexpr int kBatchViGrid = 8192;
 
 struct BatchLayout {
   size_t st, bstats, ctr, vst, vstats, wg_res, pool, total;
@@ -719,24 +738,20 @@ void batch_vi_desc(const mdp_problem *p, const mdp_model &M, const Plan &pl, int
                    int32_t *pi, VIState *st, BatchVIDesc &V)
 {
   memset(&V, 0, sizeof(V));
-  int slot = 0;
-  for (int m = 0; m < mission; ++m) slot += (int)(p->mission_mask >> m & 1u);
-  V.P.row_ptr = M.row_ptr;
-  V.P.col = M.col;
-  V.P.cnt = M.cnt;
-  V.P.R = M.reward + (int64_t)slot * pl.rows;
-  V.P.cap = M.nnz_capacity;
-  V.P.ns = (int64_t)p->nt * pl.nc;
-  V.P.na = pl.na;
-  V.P.states_per_wg = 2 * kBlock / pl.na;
-  V.P.n_blocks = (V.P.ns + V.P.states_per_wg - 1) / V.P.states_per_wg;
-  V.P.n_wg = kBatchViGrid;
-  V.P.inv_nr = 1.0 / (double)p->n_real;
+  fill_vi_params(p, &M, pl, mission, kBatchViGrid, V.P);
   V.st = st;
   V.P.st = st;
   V.v = v;
   V.v_alt = v_alt;
   V.pi = pi;
+}
+
+// LDS bytes of the widest v window among the problems of a batched sweep.
+size_t batch_win_bytes(const BatchVIDesc *vd, int n)
+{
+  size_t w = 0;
+  for (int i = 0; i < n; ++i) w = std::max(w, (size_t)vd[i].P.win_rows * vd[i].P.nx * 8);
+  return w;
 }
 
 // Persistent-build grid: resident workgroups of the device, at most one per item.
@@ -765,6 +780,7 @@ struct mdp_batch {
   int n_items = 0;
   int max_nt = 0;
   int64_t pool_cap = 0;
+  size_t win_bytes = 0;  // widest v window of the solve
   char *scratch = nullptr;
   BatchLayout L;
   BatchBuildDesc *d_bdesc = nullptr;
@@ -869,6 +885,7 @@ mdp_status mdp_batch_create(mdp_ctx *ctx, int32_t n, const mdp_problem *probs, c
   }
   std::vector<BatchItem> flat = sort_items(items);
   b->n_items = (int)flat.size();
+  b->win_bytes = batch_win_bytes(vd.data(), n);
   if ((e = batch_build_grid(b->kmax, b->near, b->lds_max, b->n_items, &b->grid_build)) != hipSuccess) {
     batch_free(b);
     return hip_fail(ctx, e, "batch occupancy");
@@ -925,12 +942,14 @@ mdp_status mdp_batch_solve(mdp_batch *b, double tol, int32_t max_sweeps, void *s
   char *sc = b->scratch;
   double *wg_res = (double *)(sc + b->L.wg_res);
   hipError_t e;
-  if ((e = launch_vi_init((VIState *)(sc + b->L.vst), b->n, s)) != hipSuccess) return hip_fail(b->ctx, e, "vi init");
+  // cold start of every problem: v = 0 and a fresh sweep state (a kernel, so
+  // that a captured graph resets them on every replay)
+  if ((e = launch_vi_reset_batched(b->d_vdesc, b->n, s)) != hipSuccess) return hip_fail(b->ctx, e, "vi reset");
   int sweeps = max_sweeps;
   if (tol > 0.0) sweeps = std::min(sweeps, b->max_nt + 1);
   for (int k = 0; k < sweeps; ++k) {
     Timed tm(b->ctx, MDP_KERNEL_VI_SWEEP, s);
-    if ((e = launch_vi_sweep_batched(b->d_vdesc, b->n, b->d_block_start, wg_res, kBatchViGrid, s)) !=
+    if ((e = launch_vi_sweep_batched(b->d_vdesc, b->n, b->d_block_start, wg_res, kBatchViGrid, b->win_bytes, s)) !=
         hipSuccess)
       return hip_fail(b->ctx, e, "batch sweep");
     if ((e = launch_vi_close_batched(b->d_vdesc, b->n, kBatchViGrid, wg_res, tol, s)) != hipSuccess)
@@ -939,7 +958,7 @@ mdp_status mdp_batch_solve(mdp_batch *b, double tol, int32_t max_sweeps, void *s
   if ((e = launch_vi_finish_batched(b->d_vdesc, b->n, (mdp_vi_stats *)(sc + b->L.vstats), s)) != hipSuccess)
     return hip_fail(b->ctx, e, "batch finish");
   Timed tm(b->ctx, MDP_KERNEL_POLICY, s);
-  if ((e = launch_policy_batched(b->d_vdesc, b->n, b->d_block_start, kBatchViGrid, s)) != hipSuccess)
+  if ((e = launch_policy_batched(b->d_vdesc, b->n, b->d_block_start, kBatchViGrid, b->win_bytes, s)) != hipSuccess)
     return hip_fail(b->ctx, e, "batch policy");
   return MDP_OK;
 }
@@ -1319,7 +1338,7 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
 
 // Upload the solve descriptors of reqs into D / bstart (device).
 mdp_status upload_vi(mdp_server *S, const std::vector<ServeReq *> &reqs, BatchVIDesc *D, int64_t *bstart,
-                     hipStream_t s)
+                     size_t *win_bytes, hipStream_t s)
 {
   const int n = (int)reqs.size();
   std::vector<BatchVIDesc> vd(n);
@@ -1329,6 +1348,7 @@ mdp_status upload_vi(mdp_server *S, const std::vector<ServeReq *> &reqs, BatchVI
     batch_vi_desc(&r->p, req_model(r), r->pl, r->mission, r->v, r->v_alt, r->pi, r->st, vd[i]);
     bs[i + 1] = bs[i] + vd[i].P.n_blocks;
   }
+  *win_bytes = batch_win_bytes(vd.data(), n);
   hipError_t e;
   if ((e = hipMemcpyAsync(D, vd.data(), sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(bstart, bs.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -1470,7 +1490,8 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   const int n_run = (int)S->running.size();
   std::vector<mdp_build_stats> hb(fresh.size());
   if (n_run > 0) {
-    if ((rc = upload_vi(S, S->running, S->d_vrun, S->d_bs_run, s)) != MDP_OK) return rc;
+    size_t win = 0;
+    if ((rc = upload_vi(S, S->running, S->d_vrun, S->d_bs_run, &win, s)) != MDP_OK) return rc;
     if ((e = launch_vi_reset_batched(S->d_vrun + n_old, n_run - n_old, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve reset");
     int k = S->cfg.sweeps_per_step;
@@ -1478,7 +1499,7 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
     k = std::max(k, 0);
     for (int j = 0; j < k; ++j) {
       Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
-      if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_run, S->d_wg_res, kBatchViGrid, s)) !=
+      if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_run, S->d_wg_res, kBatchViGrid, win, s)) !=
           hipSuccess)
         return hip_fail(S->ctx, e, "serve sweep");
       if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
@@ -1527,12 +1548,13 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   }
   if (!ret.empty()) {
     const int n = (int)ret.size();
-    if ((rc = upload_vi(S, ret, S->d_vret, S->d_bs_ret, s)) != MDP_OK) return rc;
+    size_t win = 0;
+    if ((rc = upload_vi(S, ret, S->d_vret, S->d_bs_ret, &win, s)) != MDP_OK) return rc;
     if ((e = launch_vi_finish_batched(S->d_vret, n, S->d_vstat, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve finish");
     {
       Timed tm(S->ctx, MDP_KERNEL_POLICY, s);
-      if ((e = launch_policy_batched(S->d_vret, n, S->d_bs_ret, kBatchViGrid, s)) != hipSuccess)
+      if ((e = launch_policy_batched(S->d_vret, n, S->d_bs_ret, kBatchViGrid, win, s)) != hipSuccess)
         return hip_fail(S->ctx, e, "serve policy");
     }
     std::vector<mdp_vi_stats> hf(n);

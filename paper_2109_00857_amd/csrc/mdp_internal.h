@@ -129,11 +129,44 @@ struct VIParams {
   const float *R;           // reward block of the mission
   int64_t cap;              // length of col / cnt
   int64_t ns;
-  int na, states_per_wg, n_wg;   // states per block (2 rows per thread); launched workgroups
-  int64_t n_blocks;              // blocks of states_per_wg states
+  int na, nx, ny, nc, nt, hy;
+  int states_per_wg;        // S: cells of one layer per block, S * na <= 2 * kBlock rows
+  int blocks_per_layer;     // ceil(nc / S)
+  int64_t n_blocks;         // nt * blocks_per_layer
+  int win_rows;             // grid rows of the staged window of v(t + 1); 0: gather from memory
+  int max_row;              // most entries a row can hold, min(N_sg, n_real)
+  int n_wg;                 // launched workgroups
+  int pad;
   double inv_nr, tol;
   VIState *st;
 };
+
+// LDS of the sweep / policy kernels, in doubles: Q of the block's rows and
+// the wave maxima; then (batched kernels) per-problem residuals and block
+// starts; then the window of v(t + 1).
+constexpr int kViRows = 2 * kBlock;
+constexpr int kViQ = 0;
+constexpr int kViWmax = kViQ + kViRows;
+constexpr int kViFixed = kViWmax + 8;
+constexpr int kViWinPerThread = 8;                             // window values a thread stages
+constexpr size_t kViWinBudget = (size_t)kViWinPerThread * kBlock * 8;  // bytes of the v window at most
+
+// Grid rows the v window of a block needs (rows spanned by S cells plus hy on
+// each side), or 0 when it would not fit the budget.
+inline int vi_window_rows(int nx, int ny, int hy, int S)
+{
+  int rows = (S - 1) / nx + 2 + 2 * hy;
+  if (rows > ny) rows = ny;
+  return (size_t)rows * nx * 8 <= kViWinBudget ? rows : 0;
+}
+
+// Layers a sweep recomputes when `sweeps` sweeps of the solve are behind it:
+// layers t >= nt - sweeps + 1 are final in both value buffers.
+__host__ __device__ inline int vi_active_layers(int nt, int sweeps)
+{
+  const int a = nt - sweeps + 1;
+  return a < 0 ? 0 : (a > nt ? nt : a);
+}
 
 // One problem of a batched solve (device-resident descriptor).
 struct BatchVIDesc {
@@ -147,15 +180,19 @@ struct BatchVIDesc {
 constexpr int kMaxBatch = 1024;  // problems per batch
 
 hipError_t launch_vi_init(VIState *st, int n, hipStream_t s);
-hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, hipStream_t s);
+// One sweep over layers [0, t_hi) (later layers are final and already in both
+// buffers) and its close; returns the grid used.
+hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, int t_hi, double *wg_res,
+                           hipStream_t s);
 hipError_t launch_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *block_start, double *wg_res,
-                                   int grid, hipStream_t s);
+                                   int grid, size_t win_bytes, hipStream_t s);
 hipError_t launch_vi_reset_batched(const BatchVIDesc *D, int n, hipStream_t s);
 hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s);
 hipError_t launch_vi_close_batched(const BatchVIDesc *D, int n, int grid, const double *wg_res, double tol,
                                    hipStream_t s);
 hipError_t launch_vi_finish_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s);
-hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *block_start, int grid, hipStream_t s);
+hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *block_start, int grid,
+                                 size_t win_bytes, hipStream_t s);
 hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, mdp_vi_stats *dev_stats,
                             hipStream_t s);
 hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s);

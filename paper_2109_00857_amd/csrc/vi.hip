@@ -1,63 +1,142 @@
 // Value iteration and greedy policy on the CSR model (Sec. II-B update rule).
 //
-// A workgroup takes blocks of whole states (a state's N_a rows are
-// contiguous); each thread computes two rows
+// A workgroup takes a block of S cells of one decision layer t (their S * N_a
+// rows are contiguous, at most 512; two rows per thread). For the block every
+// thread first issues all loads that do not depend on each other: the row
+// pointers and rewards of its rows, the old value of its state, its share of
+// the window of v_old(t + 1) that the rows can reach (grid rows within the
+// sub-grid half height of the block's rows), and the first entries (col, cnt)
+// of its rows. The window goes to LDS, then each thread adds its rows'
 //     Q(s, a) = R(s, a) + (sum_k cnt_k * v_old[col_k]) / N_r      (fp64)
-// adding the terms in ascending entry order, with the sinks DEAD and TARGET
-// contributing 0, then one thread per state takes max_a through LDS. The two
-// rows of a thread are walked together so their loads overlap.
+// in ascending entry order (the sinks DEAD and TARGET contribute 0), two
+// entries of each row per round, and one thread per state takes max_a Q
+// (first maximum on ties). The per-row sum has a fixed order, so every path
+// (single problem, batch, server) gives the same bits.
 //
-// Residual max_s |v_new - v_old|: in the single-problem sweep every workgroup
-// of a chip-filling grid folds its maximum into one word and the last
-// workgroup to finish closes the sweep (count, done flag, reset); later sweeps
-// of the call see the done flag and return at once, so the host enqueues the
-// sweeps without polling. In the batched sweep workgroups write one maximum
-// per problem into a [grid][problems] matrix and a small kernel closes each
-// problem's sweep (no atomics).
+// Every transition goes from layer t to layer t + 1 or to a sink, and layer
+// T - 1 reaches only sinks, so after k sweeps the layers t >= T - k hold
+// their final values whatever v0 was. A layer that was already final before
+// the previous sweep has its final value in both buffers; sweep k (0-based)
+// therefore recomputes only layers t < T - k + 1. The skipped layers would
+// reproduce their values bit for bit and add 0 to the residual, so this is
+// exactly the synchronous sweep, with the same residual and sweep count.
+//
+// Residual max_s |v_new - v_old|: every workgroup writes its maximum (per
+// problem in the batched sweep) and a small kernel closes the sweep (count,
+// done flag); later sweeps see the done flag and return at once, so the host
+// enqueues the sweeps without polling.
 #include "mdp_internal.h"
+
+#include <algorithm>
 
 namespace mdpk {
 
-constexpr int kRowsPerBlock = 2 * kBlock;
+constexpr int kViGridMax = 8192;
+constexpr int kViUnroll = 2;  // entries of each row loaded per round
 
-// Q for the rows of states [s0, s0 + nst) into q[], then per state either the
+// Loads of the next kViUnroll entries of rows [lo, hi) (a valid index when past the end).
+__device__ inline void vi_load(const VIParams &P, int64_t lo, int64_t hi, uint32_t *c, uint16_t *n)
+{
+#pragma unroll
+  for (int u = 0; u < kViUnroll; ++u) {
+    const int64_t k = lo + u;
+    const bool ok = k < hi;
+    const int64_t kk = ok ? k : 0;
+    const uint32_t cv = (uint32_t)P.col[kk];
+    const uint16_t nv = P.cnt[kk];
+    c[u] = ok ? cv : 0xffffffffu;
+    n[u] = ok ? nv : (uint16_t)0;
+  }
+}
+
+// Add loaded entries to acc in order; the window covers [wbase, wbase + wn).
+__device__ inline void vi_add(const VIParams &P, const double *vin, const double *vwin, int64_t wbase, int wn,
+                              int64_t lo, int64_t hi, const uint32_t *c, const uint16_t *n, double &acc)
+{
+  const uint32_t ns32 = (uint32_t)P.ns;
+#pragma unroll
+  for (int u = 0; u < kViUnroll; ++u) {
+    if (lo + u < hi) {
+      const uint32_t cc = c[u];
+      double vv = 0.0;
+      if (cc < ns32) {
+        const int64_t w = (int64_t)cc - wbase;
+        vv = (w >= 0 && w < wn) ? vwin[w] : vin[cc];
+      }
+      acc += (double)n[u] * vv;
+    }
+  }
+}
+
+// Q of the rows of cells [c0, c0 + S) of layer t, then per state either the
 // new value (returns the block's max |v_new - v_old|) or the first argmax.
 template <bool POLICY>
-__device__ inline double vi_block(const VIParams &P, const double *vin, double *vout, int32_t *pi, int64_t s0,
-                                  int nst, double *q)
+__device__ inline double vi_block(const VIParams &P, const double *vin, double *vout, int32_t *pi, int t, int c0,
+                                  double *sm, double *vwin)
 {
+  double *q = sm + kViQ;
   const int tid = threadIdx.x;
-  const int nrows = nst * P.na;
+  const int nst = min(P.states_per_wg, P.nc - c0);
+  const int nr = nst * P.na;
+  const int64_t s0 = (int64_t)t * P.nc + c0;
   const int64_t row0 = s0 * P.na;
-  const uint32_t ns32 = (uint32_t)P.ns;
-  int64_t k0 = 0, e0 = 0, k1 = 0, e1 = 0;
-  if (tid < nrows) {
-    k0 = P.row_ptr[row0 + tid];
-    e0 = min(P.row_ptr[row0 + tid + 1], P.cap);
-  }
-  if (tid + kBlock < nrows) {
-    k1 = P.row_ptr[row0 + tid + kBlock];
-    e1 = min(P.row_ptr[row0 + tid + kBlock + 1], P.cap);
-  }
-  k0 = max(k0, (int64_t)0);
-  k1 = max(k1, (int64_t)0);
-  double a0 = 0.0, a1 = 0.0;
-  while (k0 < e0 || k1 < e1) {
-    if (k0 < e0) {
-      const uint32_t c = (uint32_t)P.col[k0];
-      const double vv = (c < ns32) ? vin[c] : 0.0;
-      a0 += (double)P.cnt[k0] * vv;
-      ++k0;
-    }
-    if (k1 < e1) {
-      const uint32_t c = (uint32_t)P.col[k1];
-      const double vv = (c < ns32) ? vin[c] : 0.0;
-      a1 += (double)P.cnt[k1] * vv;
-      ++k1;
+  // independent loads: row pointers (clamped into col / cnt), rewards, own value
+  int64_t lo[2], hi[2];
+  float rr[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = tid + kBlock * h;
+    lo[h] = hi[h] = 0;
+    rr[h] = 0.0f;
+    if (r < nr) {
+      lo[h] = max(P.row_ptr[row0 + r], (int64_t)0);
+      hi[h] = min(min(P.row_ptr[row0 + r + 1], P.cap), lo[h] + P.max_row);
+      rr[h] = P.R[row0 + r];
     }
   }
-  if (tid < nrows) q[tid] = (double)P.R[row0 + tid] + a0 * P.inv_nr;
-  if (tid + kBlock < nrows) q[tid + kBlock] = (double)P.R[row0 + tid + kBlock] + a1 * P.inv_nr;
+  const double vself = (!POLICY && tid < nst) ? vin[s0 + tid] : 0.0;
+  int64_t wbase = 0;
+  int wn = 0;
+  if (P.win_rows > 0 && t + 1 < P.nt) {
+    const int jw0 = max(0, c0 / P.nx - P.hy);
+    const int jw1 = min(P.ny - 1, (c0 + nst - 1) / P.nx + P.hy);
+    wn = (jw1 - jw0 + 1) * P.nx;  // <= win_rows * nx <= kViWinPerThread * kBlock
+    wbase = (int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx;
+  }
+  double wv[kViWinPerThread];
+#pragma unroll
+  for (int j = 0; j < kViWinPerThread; ++j) {
+    const int k = tid + kBlock * j;
+    wv[j] = k < wn ? vin[wbase + k] : 0.0;
+  }
+  uint32_t c[2][kViUnroll];
+  uint16_t n[2][kViUnroll];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) vi_load(P, lo[h], hi[h], c[h], n[h]);
+#pragma unroll
+  for (int j = 0; j < kViWinPerThread; ++j) {
+    const int k = tid + kBlock * j;
+    if (k < wn) vwin[k] = wv[j];
+  }
+  __syncthreads();
+  double acc[2] = {0.0, 0.0};
+  for (;;) {
+    bool more = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      vi_add(P, vin, vwin, wbase, wn, lo[h], hi[h], c[h], n[h], acc[h]);
+      lo[h] += kViUnroll;
+      more = more || lo[h] < hi[h];
+    }
+    if (!more) break;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) vi_load(P, lo[h], hi[h], c[h], n[h]);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = tid + kBlock * h;
+    if (r < nr) q[r] = (double)rr[h] + acc[h] * P.inv_nr;
+  }
   __syncthreads();
   double d = 0.0;
   if (tid < nst) {
@@ -74,7 +153,7 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
       pi[s] = besta;
     } else {
       vout[s] = best;
-      d = fabs(best - vin[s]);
+      d = fabs(best - vself);
     }
   }
   __syncthreads();
@@ -94,34 +173,37 @@ __device__ inline double block_max(double d, double *wmax)
   return m;
 }
 
-// One synchronous sweep over a chip-filling grid.
-__global__ __launch_bounds__(kBlock) void k_vi_sweep(const VIParams P, const double *vin, double *vout)
+// One synchronous sweep over the blocks of layers [0, t_hi); wg_res[blockIdx]
+// gets the workgroup's max |v_new - v_old|.
+__global__ __launch_bounds__(kBlock) void k_vi_sweep(const VIParams P, const double *vin, double *vout, int t_hi,
+                                                      double *wg_res)
 {
-  __shared__ double q[kRowsPerBlock];
-  __shared__ double wmax[kBlock / 64];
+  extern __shared__ double sm[];
   if (P.st->done) return;
   double d = 0.0;
-  for (int64_t blk = blockIdx.x; blk < P.n_blocks; blk += gridDim.x) {
-    const int64_t s0 = blk * P.states_per_wg;
-    const int nst = (int)min((int64_t)P.states_per_wg, P.ns - s0);
-    d = fmax(d, vi_block<false>(P, vin, vout, nullptr, s0, nst, q));
+  const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
+  for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+    const int t = (int)(blk / P.blocks_per_layer);
+    const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
+    d = fmax(d, vi_block<false>(P, vin, vout, nullptr, t, c0, sm, sm + kViFixed));
   }
-  const double m = block_max(d, wmax);
+  const double m = block_max(d, sm + kViWmax);
+  if (threadIdx.x == 0) wg_res[blockIdx.x] = m;
+}
+
+// Close one sweep: count, last residual, done flag.
+__global__ __launch_bounds__(kBlock) void k_vi_close(const VIParams P, const double *wg_res, int grid)
+{
+  __shared__ double wmax[kBlock / 64];
+  VIState *st = P.st;
+  if (st->done) return;
+  double m = 0.0;
+  for (int w = threadIdx.x; w < grid; w += kBlock) m = fmax(m, wg_res[w]);
+  m = block_max(m, wmax);
   if (threadIdx.x == 0) {
-    atomicMax(&P.st->res_bits, (unsigned long long)__double_as_longlong(m));
-    __threadfence();
-    const unsigned int prev = atomicAdd(&P.st->wg_count, 1u);
-    if (prev == gridDim.x - 1u) {
-      __threadfence();
-      const unsigned long long rb = atomicAdd(&P.st->res_bits, 0ull);
-      const double res = __longlong_as_double((long long)rb);
-      P.st->sweeps += 1;
-      P.st->last_res = res;
-      if (res < P.tol) P.st->done = 1;
-      P.st->res_bits = 0ull;
-      P.st->wg_count = 0u;
-      __threadfence();
-    }
+    st->sweeps += 1;
+    st->last_res = m;
+    if (m < P.tol) st->done = 1;
   }
 }
 
@@ -157,11 +239,11 @@ __global__ __launch_bounds__(kBlock) void k_vi_finish(const VIParams P, double *
 
 __global__ __launch_bounds__(kBlock) void k_policy(const VIParams P, const double *v, int32_t *pi)
 {
-  __shared__ double q[kRowsPerBlock];
+  extern __shared__ double sm[];
   for (int64_t blk = blockIdx.x; blk < P.n_blocks; blk += gridDim.x) {
-    const int64_t s0 = blk * P.states_per_wg;
-    const int nst = (int)min((int64_t)P.states_per_wg, P.ns - s0);
-    vi_block<true>(P, v, nullptr, pi, s0, nst, q);
+    const int t = (int)(blk / P.blocks_per_layer);
+    const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
+    vi_block<true>(P, v, nullptr, pi, t, c0, sm, sm + kViFixed);
   }
 }
 
@@ -182,15 +264,16 @@ __device__ inline int batch_problem(const int64_t *block_start, int n, int64_t g
 
 // One synchronous sweep of every problem that has not converged. A problem
 // with an even sweep count reads v and writes v_alt, with an odd count the
-// reverse, so problems that joined at different sweeps share the launch.
+// reverse, so problems that joined at different sweeps share the launch; each
+// recomputes only its layers that are not yet final in both buffers.
 // wg_res[blockIdx][i] gets this workgroup's max residual of problem i.
 __global__ __launch_bounds__(kBlock) void k_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *block_start,
                                                               double *wg_res)
 {
-  __shared__ double q[kRowsPerBlock];
-  __shared__ double wmax[kBlock / 64];
-  __shared__ double res[kMaxBatch];
-  __shared__ int64_t bstart[kMaxBatch + 1];
+  extern __shared__ double sm[];
+  double *res = sm + kViFixed;
+  int64_t *bstart = reinterpret_cast<int64_t *>(sm + kViFixed + n);
+  double *vwin = sm + kViFixed + 2 * n + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i <= n; i += kBlock) bstart[i] = block_start[i];
   for (int i = tid; i < n; i += kBlock) res[i] = 0.0;
@@ -200,13 +283,15 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep_batched(const BatchVIDesc *
     const int i = batch_problem(bstart, n, g);
     const BatchVIDesc &d = D[i];
     if (d.st->done) continue;  // uniform per block
+    const int sweeps = d.st->sweeps;
     const int64_t blk = g - bstart[i];
-    const int64_t s0 = blk * d.P.states_per_wg;
-    const int nst = (int)min((int64_t)d.P.states_per_wg, d.P.ns - s0);
-    const bool odd = (d.st->sweeps & 1) != 0;
+    const int t = (int)(blk / d.P.blocks_per_layer);
+    if (t >= vi_active_layers(d.P.nt, sweeps)) continue;
+    const int c0 = (int)(blk - (int64_t)t * d.P.blocks_per_layer) * d.P.states_per_wg;
+    const bool odd = (sweeps & 1) != 0;
     const double *vin = odd ? d.v_alt : d.v;
     double *vout = odd ? d.v : d.v_alt;
-    const double m = block_max(vi_block<false>(d.P, vin, vout, nullptr, s0, nst, q), wmax);
+    const double m = block_max(vi_block<false>(d.P, vin, vout, nullptr, t, c0, sm, vwin), sm + kViWmax);
     if (tid == 0) res[i] = fmax(res[i], m);
   }
   __syncthreads();
@@ -281,30 +366,56 @@ __global__ void k_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *o
 
 __global__ __launch_bounds__(kBlock) void k_policy_batched(const BatchVIDesc *D, int n, const int64_t *block_start)
 {
-  __shared__ double q[kRowsPerBlock];
-  __shared__ int64_t bstart[kMaxBatch + 1];
+  extern __shared__ double sm[];
+  int64_t *bstart = reinterpret_cast<int64_t *>(sm + kViFixed + n);
+  double *vwin = sm + kViFixed + 2 * n + 1;
   for (int i = threadIdx.x; i <= n; i += kBlock) bstart[i] = block_start[i];
   __syncthreads();
   const int64_t total = bstart[n];
   for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
     const int i = batch_problem(bstart, n, g);
     const BatchVIDesc &d = D[i];
-    const int64_t s0 = (g - bstart[i]) * d.P.states_per_wg;
-    const int nst = (int)min((int64_t)d.P.states_per_wg, d.P.ns - s0);
-    vi_block<true>(d.P, d.v, nullptr, d.pi, s0, nst, q);
+    const int64_t blk = g - bstart[i];
+    const int t = (int)(blk / d.P.blocks_per_layer);
+    const int c0 = (int)(blk - (int64_t)t * d.P.blocks_per_layer) * d.P.states_per_wg;
+    vi_block<true>(d.P, d.v, nullptr, d.pi, t, c0, sm, vwin);
   }
 }
 
 // ------------------------------------------------------------------ launchers
+// Raise a kernel's dynamic-LDS limit to whatever its static LDS leaves free.
+static hipError_t allow_lds(const void *kern, bool &done)
+{
+  if (done) return hipSuccess;
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, kern);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - fa.sharedSizeBytes));
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+static size_t single_lds(const VIParams &P) { return (size_t)kViFixed * 8 + (size_t)P.win_rows * P.nx * 8; }
+
+static size_t batch_lds(int n, size_t win_bytes) { return ((size_t)kViFixed + 2 * (size_t)n + 2) * 8 + win_bytes; }
+
 hipError_t launch_vi_init(VIState *st, int n, hipStream_t s)
 {
   hipLaunchKernelGGL(k_vi_init, dim3((n + 63) / 64), dim3(64), 0, s, st, n);
   return hipGetLastError();
 }
 
-hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, hipStream_t s)
+hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, int t_hi, double *wg_res,
+                           hipStream_t s)
 {
-  hipLaunchKernelGGL(k_vi_sweep, dim3(P.n_wg), dim3(kBlock), 0, s, P, vin, vout);
+  static bool attr = false;
+  hipError_t e = allow_lds((const void *)k_vi_sweep, attr);
+  if (e != hipSuccess) return e;
+  const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nb, std::min(P.n_wg, kViGridMax)));
+  hipLaunchKernelGGL(k_vi_sweep, dim3(grid), dim3(kBlock), single_lds(P), s, P, vin, vout, t_hi, wg_res);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vi_close, dim3(1), dim3(kBlock), 0, s, P, (const double *)wg_res, grid);
   return hipGetLastError();
 }
 
@@ -319,14 +430,35 @@ hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, m
 
 hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s)
 {
-  hipLaunchKernelGGL(k_policy, dim3(P.n_wg), dim3(kBlock), 0, s, P, v, pi);
+  static bool attr = false;
+  hipError_t e = allow_lds((const void *)k_policy, attr);
+  if (e != hipSuccess) return e;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(P.n_blocks, kViGridMax));
+  hipLaunchKernelGGL(k_policy, dim3(grid), dim3(kBlock), single_lds(P), s, P, v, pi);
   return hipGetLastError();
 }
 
 hipError_t launch_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *block_start, double *wg_res,
-                                   int grid, hipStream_t s)
+                                   int grid, size_t win_bytes, hipStream_t s)
 {
-  hipLaunchKernelGGL(k_vi_sweep_batched, dim3(grid), dim3(kBlock), 0, s, D, n, block_start, wg_res);
+  static bool attr = false;
+  hipError_t e = allow_lds((const void *)k_vi_sweep_batched, attr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vi_sweep_batched, dim3(grid), dim3(kBlock), batch_lds(n, win_bytes), s, D, n, block_start,
+                     wg_res);
+  return hipGetLastError();
+}
+
+hipError_t launch_vi_close_batched(const BatchVIDesc *D, int n, int grid, const double *wg_res, double tol,
+                                   hipStream_t s)
+{
+  hipLaunchKernelGGL(k_vi_close_batched, dim3(n), dim3(kBlock), 0, s, D, n, grid, wg_res, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_vi_finish_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_vi_finish_batched, dim3(256, n), dim3(kBlock), 0, s, D, n, out);
   return hipGetLastError();
 }
 
@@ -344,22 +476,13 @@ hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *o
   return hipGetLastError();
 }
 
-hipError_t launch_vi_close_batched(const BatchVIDesc *D, int n, int grid, const double *wg_res, double tol,
-                                   hipStream_t s)
+hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *block_start, int grid,
+                                 size_t win_bytes, hipStream_t s)
 {
-  hipLaunchKernelGGL(k_vi_close_batched, dim3(n), dim3(kBlock), 0, s, D, n, grid, wg_res, tol);
-  return hipGetLastError();
-}
-
-hipError_t launch_vi_finish_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s)
-{
-  hipLaunchKernelGGL(k_vi_finish_batched, dim3(256, n), dim3(kBlock), 0, s, D, n, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *block_start, int grid, hipStream_t s)
-{
-  hipLaunchKernelGGL(k_policy_batched, dim3(grid), dim3(kBlock), 0, s, D, n, block_start);
+  static bool attr = false;
+  hipError_t e = allow_lds((const void *)k_policy_batched, attr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_policy_batched, dim3(grid), dim3(kBlock), batch_lds(n, win_bytes), s, D, n, block_start);
   return hipGetLastError();
 }
 

@@ -121,6 +121,7 @@ def test_batch_graph_replays(planner):
     b.solve()
     torch.cuda.synchronize()
     nnz = [s["nnz"] for s in b.stats()[0]]
+    ref_sweeps = [s["sweeps"] for s in b.stats()[1]]
     ref_models = [{k: t.clone() for k, t in m.items()} for m in b.models]
     ref_v = [t.clone() for t in b.v]
     ref_pi = [t.clone() for t in b.pi]
@@ -140,6 +141,8 @@ def test_batch_graph_replays(planner):
         _ = torch.ones(1024, device=planner.device).sum().item()  # eager work between replays
         bs, vs = b.stats()
         assert all(x["status"] == 0 for x in bs) and all(x["status"] == 0 for x in vs), (rep, bs, vs)
+        # every replay starts cold: the same sweep counts as the eager solve
+        assert [x["sweeps"] for x in vs] == ref_sweeps, (rep, vs)
         for i in range(len(ws)):
             for k in ("row_ptr", "reward"):
                 assert _same(b.models[i][k], ref_models[i][k]), (rep, i, k)

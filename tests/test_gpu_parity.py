@@ -191,3 +191,31 @@ def test_vi_layered_residual(planner, ora):
     v2, st2 = planner.value_iterate(w.problem, model, 0, tol=0.0, max_sweeps=9)
     assert st2["sweeps"] == 9 and st2["status"] != 0
     assert v.cpu().numpy().tobytes() == v2.cpu().numpy().tobytes()
+
+
+def test_vi_partial_sweeps_and_warm_start(planner, ora):
+    """k synchronous sweeps (k < nt + 1, so layers are still moving) match the
+    oracle's k Jacobi sweeps, and a random warm start converges to the cold
+    start's values bit for bit within nt + 1 sweeps (every layer's final value
+    depends only on the model, whatever v0 was)."""
+    import torch
+
+    w = W.config1(nt=8, n_real=200, sub_h=3)
+    env = planner.upload_env(w)
+    model, stats = planner.build(w.problem, env)
+    om = ora.build_model(w)
+    _, _, w_ora = ora.backward(w, om, 0)
+    for k in (1, 2, 4, 7):
+        v_gpu, st = planner.value_iterate(w.problem, model, 0, tol=0.0, max_sweeps=k)
+        assert st["sweeps"] == k
+        v_ora, k_ora, _ = ora.jacobi(w, om, 0, tol=0.0, max_sweeps=k)
+        assert k_ora == k
+        err = np.abs(v_gpu.cpu().numpy() - v_ora)
+        assert (err <= 1e-5 * (w_ora + 1.0)).all(), (k, float(err.max()))
+    v_cold, st_cold = planner.value_iterate(w.problem, model, 0)
+    rng = np.random.default_rng(5)
+    v0 = torch.from_numpy(rng.normal(0.0, 100.0, w.n_states)).to(planner.device)
+    v_warm, st_warm = planner.value_iterate(w.problem, model, 0, v0=v0)
+    assert st_cold["status"] == 0 and st_warm["status"] == 0
+    assert st_warm["sweeps"] <= w.problem["nt"] + 1
+    assert v_warm.cpu().numpy().tobytes() == v_cold.cpu().numpy().tobytes()
