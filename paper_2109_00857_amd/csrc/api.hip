@@ -651,7 +651,7 @@ const char *batch_layout(int n, const mdp_problem *probs, int64_t pool_entries, 
   };
   L.st = take(sizeof(BuildState) * n);
   L.bstats = take(sizeof(mdp_build_stats) * n);
-  L.ctr = take(64);
+  L.ctr = take(4 * kMaxBuildGroups + 8);  // group work counters, staging pool top
   L.vst = take(sizeof(VIState) * n);
   L.vstats = take(sizeof(mdp_vi_stats) * n);
   L.wg_res = take(sizeof(double) * (size_t)kBatchViGrid * n);
@@ -721,18 +721,6 @@ const char *batch_build_desc(int inst, const mdp_problem *p, const mdp_env *env,
   return nullptr;
 }
 
-// Work list in descending cost (ties keep problem, layer, tile order).
-std::vector<BatchItem> sort_items(std::vector<std::pair<double, BatchItem>> &items)
-{
-  std::stable_sort(items.begin(), items.end(),
-                   [](const std::pair<double, BatchItem> &x, const std::pair<double, BatchItem> &y) {
-                     return x.first > y.first;
-                   });
-  std::vector<BatchItem> flat(items.size());
-  for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].second;
-  return flat;
-}
-
 // Solve descriptor of one problem of a batch.
 void batch_vi_desc(const mdp_problem *p, const mdp_model &M, const Plan &pl, int mission, double *v, double *v_alt,
                    int32_t *pi, VIState *st, BatchVIDesc &V)
@@ -768,15 +756,96 @@ hipError_t batch_build_grid(int kmax, bool near, size_t lds, int n_items, int *g
   return hipSuccess;
 }
 
+// One persistent launch of a batched build: problems sharing a kernel variant.
+struct BuildGroup {
+  int kmax = 4;
+  bool near = false;
+  int occ = 0;  // workgroups per CU that the LDS allows
+  size_t lds = 0;
+  int first = 0, count = 0, grid = 1;
+};
+
+// Order the work list by group (mode bound, near-edge counting) and, inside a
+// group, by descending cost; fill each group's item range and grid.
+hipError_t plan_build_groups(std::vector<std::pair<double, BatchItem>> &items, const std::vector<int> &kmax_of,
+                             const std::vector<char> &near_of, const std::vector<size_t> &lds_of,
+                             std::vector<BatchItem> &flat, std::vector<BuildGroup> &groups)
+{
+  const int n = (int)kmax_of.size();
+  std::vector<int> gid(n);
+  groups.clear();
+  for (int i = 0; i < n; ++i) {
+    // problems whose histograms allow the same number of resident workgroups
+    // share a launch, so no problem runs at a larger problem's occupancy
+    const int occ = (int)std::min<size_t>(8, kLdsLimit / std::max<size_t>(lds_of[i], 1));
+    int g = 0;
+    while (g < (int)groups.size() &&
+           !(groups[g].kmax == kmax_of[i] && groups[g].near == (near_of[i] != 0) && groups[g].occ == occ))
+      ++g;
+    if (g == (int)groups.size()) {
+      if ((int)groups.size() == kMaxBuildGroups) return hipErrorInvalidValue;
+      BuildGroup G;
+      G.kmax = kmax_of[i];
+      G.near = near_of[i] != 0;
+      G.occ = occ;
+      groups.push_back(G);
+    }
+    groups[g].lds = std::max(groups[g].lds, lds_of[i]);
+    gid[i] = g;
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const std::pair<double, BatchItem> &x, const std::pair<double, BatchItem> &y) {
+                     const int gx = gid[x.second.inst], gy = gid[y.second.inst];
+                     return gx != gy ? gx < gy : x.first > y.first;
+                   });
+  flat.resize(items.size());
+  for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].second;
+  for (size_t k = 0; k < flat.size(); ++k) {
+    BuildGroup &G = groups[gid[flat[k].inst]];
+    if (G.count == 0) G.first = (int)k;
+    ++G.count;
+  }
+  for (BuildGroup &G : groups) {
+    hipError_t e = batch_build_grid(G.kmax, G.near, G.lds, std::max(G.count, 1), &G.grid);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Enqueue the persistent launches of a batched build (after its init kernel).
+hipError_t enqueue_build_groups(mdp_ctx *ctx, const BatchBuildDesc *D, const BatchItem *d_items,
+                                const std::vector<BuildGroup> &groups, unsigned int *counters, uint64_t *pool,
+                                unsigned long long *pool_top, int64_t pool_cap, hipStream_t s)
+{
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const BuildGroup &G = groups[g];
+    if (G.count == 0) continue;
+    Timed tm(ctx, MDP_KERNEL_BUILD, s);
+    hipError_t e = launch_batch_build(D, d_items + G.first, G.count, counters + g, pool, pool_top, pool_cap, G.kmax,
+                                      G.near, G.lds, G.grid, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Per-sweep tables of the blocks each problem recomputes: table j (n + 1
+// entries) for problems that have sweeps[i] + j sweeps behind them.
+void active_block_tables(const BatchVIDesc *vd, const int *sweeps, int n, int n_tables, std::vector<int64_t> &out)
+{
+  out.assign((size_t)n_tables * (n + 1), 0);
+  for (int j = 0; j < n_tables; ++j) {
+    int64_t *tab = &out[(size_t)j * (n + 1)];
+    for (int i = 0; i < n; ++i)
+      tab[i + 1] = tab[i] + (int64_t)vi_active_layers(vd[i].P.nt, sweeps[i] + j) * vd[i].P.blocks_per_layer;
+  }
+}
+
 }  // namespace
 
 struct mdp_batch {
   mdp_ctx *ctx = nullptr;
   int n = 0;
-  int kmax = 4;
-  bool near = false;
-  size_t lds_max = 0;
-  int grid_build = 0;
+  std::vector<BuildGroup> groups;
   int n_items = 0;
   int max_nt = 0;
   int64_t pool_cap = 0;
@@ -787,7 +856,8 @@ struct mdp_batch {
   BatchVIDesc *d_vdesc = nullptr;
   BatchItem *d_items = nullptr;
   float *d_tabs = nullptr;
-  int64_t *d_block_start = nullptr;
+  int64_t *d_block_start = nullptr;  // every block of every problem (policy)
+  int64_t *d_bs_sweeps = nullptr;    // [max_nt + 2][n + 1]: blocks recomputed by sweep k
   hipGraphExec_t gexec = nullptr;
 };
 
@@ -812,6 +882,7 @@ static void batch_free(mdp_batch *b)
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_tabs) (void)hipFree(b->d_tabs);
   if (b->d_block_start) (void)hipFree(b->d_block_start);
+  if (b->d_bs_sweeps) (void)hipFree(b->d_bs_sweeps);
   delete b;
 }
 
@@ -838,6 +909,9 @@ mdp_status mdp_batch_create(mdp_ctx *ctx, int32_t n, const mdp_problem *probs, c
   std::vector<float> tabs((size_t)n * 2 * kMaxA, 0.0f);
   std::vector<int64_t> block_start(n + 1, 0);
   std::vector<std::pair<double, BatchItem>> items;
+  std::vector<int> kmax_of(n);
+  std::vector<char> near_of(n);
+  std::vector<size_t> lds_of(n);
   mdp_batch *b = new mdp_batch();
   b->ctx = ctx;
   b->n = n;
@@ -875,25 +949,31 @@ mdp_status mdp_batch_create(mdp_ctx *ctx, int32_t n, const mdp_problem *probs, c
       batch_free(b);
       return MDP_E_INVALID;
     }
-    b->near = b->near || bd[i].near_asked;
-    b->kmax = std::max(b->kmax, pl.kmax);
-    b->lds_max = std::max(b->lds_max, pl.lds);
+    kmax_of[i] = pl.kmax;
+    near_of[i] = (char)bd[i].near_asked;
+    lds_of[i] = pl.lds;
     b->max_nt = std::max(b->max_nt, p->nt);
     batch_vi_desc(p, M, pl, mission, d_v[i], (double *)(sc + L.v_alt[i]), d_pi[i], (VIState *)(sc + L.vst) + i,
                   vd[i]);
     block_start[i + 1] = block_start[i] + vd[i].P.n_blocks;
   }
-  std::vector<BatchItem> flat = sort_items(items);
-  b->n_items = (int)flat.size();
-  b->win_bytes = batch_win_bytes(vd.data(), n);
-  if ((e = batch_build_grid(b->kmax, b->near, b->lds_max, b->n_items, &b->grid_build)) != hipSuccess) {
+  std::vector<BatchItem> flat;
+  if ((e = plan_build_groups(items, kmax_of, near_of, lds_of, flat, b->groups)) != hipSuccess) {
     batch_free(b);
     return hip_fail(ctx, e, "batch occupancy");
   }
+  b->n_items = (int)flat.size();
+  b->win_bytes = batch_win_bytes(vd.data(), n);
+  std::vector<int64_t> bs_sweeps;
+  const std::vector<int> zero(n, 0);
+  active_block_tables(vd.data(), zero.data(), n, b->max_nt + 2, bs_sweeps);
   if ((e = hipMalloc((void **)&b->d_bdesc, sizeof(BatchBuildDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&b->d_vdesc, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&b->d_items, sizeof(BatchItem) * flat.size())) != hipSuccess ||
       (e = hipMalloc((void **)&b->d_block_start, sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = hipMalloc((void **)&b->d_bs_sweeps, sizeof(int64_t) * bs_sweeps.size())) != hipSuccess ||
+      (e = hipMemcpy(b->d_bs_sweeps, bs_sweeps.data(), sizeof(int64_t) * bs_sweeps.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
       (e = hipMemcpy(b->d_bdesc, bd.data(), sizeof(BatchBuildDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b->d_vdesc, vd.data(), sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b->d_items, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -912,18 +992,15 @@ mdp_status mdp_batch_build(mdp_batch *b, void *stream)
   if (!b) return MDP_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   char *sc = b->scratch;
-  unsigned int *counter = (unsigned int *)(sc + b->L.ctr);
-  unsigned long long *pool_top = (unsigned long long *)(sc + b->L.ctr + 8);
+  unsigned int *counter = (unsigned int *)(sc + b->L.ctr);  // one per group
+  unsigned long long *pool_top = (unsigned long long *)(sc + b->L.ctr + 4 * kMaxBuildGroups);
   uint64_t *pool = (uint64_t *)(sc + b->L.pool);
   hipError_t e;
   if ((e = launch_batch_build_init(b->d_bdesc, b->n, counter, pool_top, s)) != hipSuccess)
     return hip_fail(b->ctx, e, "batch init");
-  {
-    Timed tm(b->ctx, MDP_KERNEL_BUILD, s);
-    if ((e = launch_batch_build(b->d_bdesc, b->d_items, b->n_items, counter, pool, pool_top, b->pool_cap, b->kmax,
-                                b->near, b->lds_max, b->grid_build, s)) != hipSuccess)
-      return hip_fail(b->ctx, e, "batch build");
-  }
+  if ((e = enqueue_build_groups(b->ctx, b->d_bdesc, b->d_items, b->groups, counter, pool, pool_top, b->pool_cap,
+                                 s)) != hipSuccess)
+    return hip_fail(b->ctx, e, "batch build");
   if ((e = launch_batch_scan(b->d_bdesc, b->n, s)) != hipSuccess) return hip_fail(b->ctx, e, "batch scan");
   {
     Timed tm(b->ctx, MDP_KERNEL_COPY, s);
@@ -949,7 +1026,8 @@ mdp_status mdp_batch_solve(mdp_batch *b, double tol, int32_t max_sweeps, void *s
   if (tol > 0.0) sweeps = std::min(sweeps, b->max_nt + 1);
   for (int k = 0; k < sweeps; ++k) {
     Timed tm(b->ctx, MDP_KERNEL_VI_SWEEP, s);
-    if ((e = launch_vi_sweep_batched(b->d_vdesc, b->n, b->d_block_start, wg_res, kBatchViGrid, b->win_bytes, s)) !=
+    if ((e = launch_vi_sweep_batched(b->d_vdesc, b->n, b->d_bs_sweeps + (size_t)std::min(k, b->max_nt + 1) * (b->n + 1),
+                                       wg_res, kBatchViGrid, b->win_bytes, s)) !=
         hipSuccess)
       return hip_fail(b->ctx, e, "batch sweep");
     if ((e = launch_vi_close_batched(b->d_vdesc, b->n, kBatchViGrid, wg_res, tol, s)) != hipSuccess)
@@ -1155,6 +1233,7 @@ struct mdp_server {
   BatchBuildDesc *d_bdesc = nullptr;
   BatchVIDesc *d_vrun = nullptr, *d_vret = nullptr;
   int64_t *d_bs_run = nullptr, *d_bs_ret = nullptr;
+  int64_t *d_bs_sweeps = nullptr;  // [sweeps_per_step][max_inflight + 1]
   double *d_wg_res = nullptr;
   mdp_vi_stats *d_vstat = nullptr;
   float *d_tabs = nullptr;
@@ -1169,7 +1248,7 @@ void serve_free_all(mdp_server *S)
 {
   for (ServeReq *r : S->queue) delete r;
   for (ServeReq *r : S->running) delete r;
-  void *bufs[] = {S->d_bdesc, S->d_vrun, S->d_vret, S->d_bs_run, S->d_bs_ret,
+  void *bufs[] = {S->d_bdesc, S->d_vrun, S->d_vret, S->d_bs_run, S->d_bs_ret, S->d_bs_sweeps,
                   S->d_wg_res, S->d_vstat, S->d_tabs, S->d_items, S->d_ctr};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
@@ -1235,7 +1314,7 @@ mdp_model req_model(const ServeReq *r)
 
 size_t build_block_bytes(const std::vector<ServeReq *> &fresh)
 {
-  size_t b = align_up(64);  // work counter and staging pool top
+  size_t b = align_up(4 * kMaxBuildGroups + 8);  // group work counters and staging pool top
   for (const ServeReq *r : fresh) b += r->z.build;
   return b;
 }
@@ -1249,16 +1328,16 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
   std::vector<BatchBuildDesc> bd(n);
   std::vector<float> tabs((size_t)n * 2 * kMaxA, 0.0f);
   std::vector<std::pair<double, BatchItem>> items;
-  size_t o = align_up(64);
-  unsigned int *counter = (unsigned int *)blk;
-  unsigned long long *pool_top = (unsigned long long *)(blk + 8);
+  size_t o = align_up(4 * kMaxBuildGroups + 8);
+  unsigned int *counter = (unsigned int *)blk;  // one per group
+  unsigned long long *pool_top = (unsigned long long *)(blk + 4 * kMaxBuildGroups);
   // per-request scratch first, staging pool entries of every request last
   std::vector<BuildScratch> B(n);
   mdp_build_stats *bstats = nullptr;
   int64_t pool_cap = 0;
-  bool near = false;
-  int kmax = 4;
-  size_t lds = 0;
+  std::vector<int> kmax_of(n);
+  std::vector<char> near_of(n);
+  std::vector<size_t> lds_of(n);
   {
     BuildState *st = (BuildState *)(blk + o);
     o += align_up(sizeof(BuildState) * n);
@@ -1290,12 +1369,15 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
       set_err(S->ctx, "request %lld: %s", (long long)r->tag, m);
       return MDP_E_INVALID;
     }
-    near = near || bd[i].near_asked;
-    kmax = std::max(kmax, r->pl.kmax);
-    lds = std::max(lds, r->pl.lds);
+    kmax_of[i] = r->pl.kmax;
+    near_of[i] = (char)bd[i].near_asked;
+    lds_of[i] = r->pl.lds;
   }
-  std::vector<BatchItem> flat = sort_items(items);
+  std::vector<BatchItem> flat;
+  std::vector<BuildGroup> groups;
   hipError_t e;
+  if ((e = plan_build_groups(items, kmax_of, near_of, lds_of, flat, groups)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve occupancy");
   if (flat.size() > S->items_cap) {
     if (S->d_items) (void)hipFree(S->d_items);
     S->d_items = nullptr;
@@ -1304,9 +1386,6 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
       return hip_fail(S->ctx, e, "serve items");
     S->items_cap = flat.size();
   }
-  int grid = 1;
-  if ((e = batch_build_grid(kmax, near, lds, (int)flat.size(), &grid)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve occupancy");
   if ((e = hipMemcpyAsync(S->d_bdesc, bd.data(), sizeof(BatchBuildDesc) * n, hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(S->d_tabs, tabs.data(), sizeof(float) * tabs.size(), hipMemcpyHostToDevice, s)) !=
@@ -1318,12 +1397,9 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(S->ctx, e, "serve sync");
   if ((e = launch_batch_build_init(S->d_bdesc, n, counter, pool_top, s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve build init");
-  {
-    Timed tm(S->ctx, MDP_KERNEL_BUILD, s);
-    if ((e = launch_batch_build(S->d_bdesc, S->d_items, (int)flat.size(), counter, pool, pool_top, pool_cap, kmax,
-                                near, lds, grid, s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve build");
-  }
+  if ((e = enqueue_build_groups(S->ctx, S->d_bdesc, S->d_items, groups, counter, pool, pool_top, pool_cap, s)) !=
+      hipSuccess)
+    return hip_fail(S->ctx, e, "serve build");
   if ((e = launch_batch_scan(S->d_bdesc, n, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve scan");
   {
     Timed tm(S->ctx, MDP_KERNEL_COPY, s);
@@ -1338,10 +1414,12 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
 
 // Upload the solve descriptors of reqs into D / bstart (device).
 mdp_status upload_vi(mdp_server *S, const std::vector<ServeReq *> &reqs, BatchVIDesc *D, int64_t *bstart,
-                     size_t *win_bytes, hipStream_t s)
+                     size_t *win_bytes, hipStream_t s, std::vector<BatchVIDesc> *desc_out = nullptr)
 {
   const int n = (int)reqs.size();
-  std::vector<BatchVIDesc> vd(n);
+  std::vector<BatchVIDesc> local;
+  std::vector<BatchVIDesc> &vd = desc_out ? *desc_out : local;
+  vd.resize(n);
   std::vector<int64_t> bs(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     ServeReq *r = reqs[i];
@@ -1367,7 +1445,7 @@ mdp_status mdp_server_footprint(const mdp_problem *p, size_t *bytes)
   Plan pl;
   if (make_plan(p, pl)) return MDP_E_INVALID;
   const ReqSizes z = req_sizes(p, pl);
-  *bytes = z.keep + z.col + z.cnt + z.build + align_up(64);
+  *bytes = z.keep + z.col + z.cnt + z.build + align_up(4 * kMaxBuildGroups + 8);
   return MDP_OK;
 }
 
@@ -1376,8 +1454,9 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
 {
   if (!ctx || !cfg || !out) return MDP_E_INVALID;
   *out = nullptr;
-  if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxBatch || cfg->sweeps_per_step < 1 || cfg->max_sweeps < 1) {
-    set_err(ctx, "max_inflight must be in [1, 1024], sweeps_per_step and max_sweeps >= 1");
+  if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxBatch || cfg->sweeps_per_step < 1 ||
+      cfg->sweeps_per_step > 256 || cfg->max_sweeps < 1) {
+    set_err(ctx, "max_inflight must be in [1, 1024], sweeps_per_step in [1, 256], max_sweeps >= 1");
     return MDP_E_INVALID;
   }
   if (!is_device_ptr(pool) || pool_bytes < kAlign) {
@@ -1397,6 +1476,7 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
       (e = hipMalloc((void **)&S->d_vret, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_bs_run, sizeof(int64_t) * (n + 1))) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_bs_ret, sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_bs_sweeps, sizeof(int64_t) * (n + 1) * cfg->sweeps_per_step)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_wg_res, sizeof(double) * kBatchViGrid * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vstat, sizeof(mdp_vi_stats) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_tabs, sizeof(float) * 2 * kMaxA * n)) != hipSuccess) {
@@ -1434,7 +1514,7 @@ mdp_status mdp_server_submit(mdp_server *S, const mdp_problem *p, const mdp_env 
     return MDP_E_INVALID;
   }
   r->z = req_sizes(&r->p, r->pl);
-  if (r->z.keep + r->z.col + r->z.cnt + r->z.build + align_up(64) > S->pool_bytes) {
+  if (r->z.keep + r->z.col + r->z.cnt + r->z.build + align_up(4 * kMaxBuildGroups + 8) > S->pool_bytes) {
     set_err(S->ctx, "request %lld needs more than the whole pool", (long long)tag);
     delete r;
     return MDP_E_CAPACITY;
@@ -1491,16 +1571,25 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   std::vector<mdp_build_stats> hb(fresh.size());
   if (n_run > 0) {
     size_t win = 0;
-    if ((rc = upload_vi(S, S->running, S->d_vrun, S->d_bs_run, &win, s)) != MDP_OK) return rc;
+    std::vector<BatchVIDesc> vd;
+    if ((rc = upload_vi(S, S->running, S->d_vrun, S->d_bs_run, &win, s, &vd)) != MDP_OK) return rc;
     if ((e = launch_vi_reset_batched(S->d_vrun + n_old, n_run - n_old, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve reset");
     int k = S->cfg.sweeps_per_step;
     for (ServeReq *r : S->running) k = std::min(k, r->limit - r->sweeps);
     k = std::max(k, 0);
+    std::vector<int> done_sweeps(n_run);
+    for (int i = 0; i < n_run; ++i) done_sweeps[i] = S->running[i]->sweeps;
+    std::vector<int64_t> tabs;
+    active_block_tables(vd.data(), done_sweeps.data(), n_run, std::max(k, 1), tabs);
+    if ((e = hipMemcpyAsync(S->d_bs_sweeps, tabs.data(), sizeof(int64_t) * tabs.size(), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve sweep tables");
     for (int j = 0; j < k; ++j) {
       Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
-      if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_run, S->d_wg_res, kBatchViGrid, win, s)) !=
-          hipSuccess)
+      if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_sweeps + (size_t)j * (n_run + 1), S->d_wg_res,
+                                       kBatchViGrid, win, s)) != hipSuccess)
         return hip_fail(S->ctx, e, "serve sweep");
       if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
         return hip_fail(S->ctx, e, "serve close");

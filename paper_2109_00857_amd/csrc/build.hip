@@ -114,8 +114,8 @@ struct TileOut {
 
 // One tile of cells at layer t, every action of those cells, every realization.
 // POOL: entries go to a bump-allocated pool slot instead of O.stage.
-template <int KMAX, bool PACK16, bool NEAR, bool POOL>
-__device__ void build_tile(const BuildParams &P, const int t, const int tile, BuildState *bst,
+template <int KMAX, bool PACK16, bool NEAR, bool POOL, typename PT>
+__device__ void build_tile(const PT &P, const int t, const int tile, BuildState *bst,
                            const TileOut &O, uint32_t *lds)
 {
   const int HW = P.hw;                              // words per bin (power of 2)
@@ -608,10 +608,8 @@ __global__ void k_batch_build_init(BatchBuildDesc *D, int n, unsigned int *count
                                    unsigned long long *pool_top)
 {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    *counter = 0u;
-    *pool_top = 0ull;
-  }
+  if (i < kMaxBuildGroups) counter[i] = 0u;
+  if (i == 0) *pool_top = 0ull;
   if (i < n) {
     BuildState *st = D[i].st;
     st->n_escape = 0;
@@ -635,23 +633,26 @@ __global__ __launch_bounds__(kBlock) void k_build_batched(const BatchBuildDesc *
   for (;;) {
     if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
     __syncthreads();
-    const int it = item_s;
+    const int it = __builtin_amdgcn_readfirstlane(item_s);  // uniform: descriptor loads go scalar
     __syncthreads();
     if (it >= n_items) break;
-    const BatchItem w = items[it];
-    const BatchBuildDesc &d = D[w.inst];
-    const int64_t local = (int64_t)w.t * d.P.tiles_per_layer + w.tile;
+    const BatchItem w = load_const(items + it);
+    // descriptor fields are read in place through the constant address space
+    typedef const __attribute__((address_space(4))) BatchBuildDesc CDesc;
+    CDesc &d = *(CDesc *)(uintptr_t)(D + w.inst);
+    auto &P = d.P;
+    const int64_t local = (int64_t)w.t * P.tiles_per_layer + w.tile;
     TileOut O;
     O.row_nnz = d.row_nnz;
     O.row_off = d.row_off;
-    O.row_base = ((int64_t)w.t * d.P.nc + (int64_t)w.tile * d.P.cells_per_tile) * d.P.na;
+    O.row_base = ((int64_t)w.t * P.nc + (int64_t)w.tile * P.cells_per_tile) * P.na;
     O.stage = nullptr;
     O.total_out = d.item_total + local;
     O.pool = pool;
     O.pool_top = pool_top;
     O.pool_cap = pool_cap;
     O.base_out = d.item_base + local;
-    build_tile<KMAX, true, NEAR, true>(d.P, w.t, w.tile, d.st, O, lds);
+    build_tile<KMAX, true, NEAR, true>(P, w.t, w.tile, d.st, O, lds);
   }
 }
 

@@ -83,10 +83,31 @@ struct BatchBuildDesc {
   int pad;
 };
 
+// A batched build runs one persistent launch per group of problems that share
+// the kernel variant (mode bound, near-edge counting) and occupancy; each group
+// has its own work counter.
+constexpr int kMaxBuildGroups = 32;
+
 // Work item of the persistent batched build: problem, layer, tile.
 struct BatchItem {
   int inst, t, tile, pad;
 };
+
+// Copy of an entry of a device table that no kernel writes while it is read,
+// fetched through the constant address space: at a wave-uniform address the
+// words arrive by scalar loads instead of occupying vector registers.
+template <typename T>
+__device__ inline T load_const(const T *p)
+{
+  static_assert(sizeof(T) % 4 == 0, "word-sized table entries");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  const cword *src = (const cword *)(uintptr_t)p;
+  T out;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
 
 // Launchers (return hipError_t of the launch)
 hipError_t launch_fill_tab(const ActionTables &T, float *tab, hipStream_t s);

@@ -262,36 +262,48 @@ __device__ inline int batch_problem(const int64_t *block_start, int n, int64_t g
   return lo;
 }
 
-// One synchronous sweep of every problem that has not converged. A problem
-// with an even sweep count reads v and writes v_alt, with an odd count the
-// reverse, so problems that joined at different sweeps share the launch; each
-// recomputes only its layers that are not yet final in both buffers.
-// wg_res[blockIdx][i] gets this workgroup's max residual of problem i.
+// One synchronous sweep of every problem that has not converged. block_start
+// lists, per problem, the blocks of the layers this sweep recomputes (layers
+// t < nt - k + 1 after k sweeps, computed by the host). A problem with an even
+// sweep count reads v and writes v_alt, with an odd count the reverse, so
+// problems that joined at different sweeps share the launch. Sweep counts and
+// done flags are read once per workgroup. wg_res[blockIdx][i] gets this
+// workgroup's max residual of problem i.
 __global__ __launch_bounds__(kBlock) void k_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *block_start,
                                                               double *wg_res)
 {
   extern __shared__ double sm[];
   double *res = sm + kViFixed;
   int64_t *bstart = reinterpret_cast<int64_t *>(sm + kViFixed + n);
-  double *vwin = sm + kViFixed + 2 * n + 1;
+  int2 *stc = reinterpret_cast<int2 *>(sm + kViFixed + 2 * n + 1);  // (sweeps, done) per problem
+  double *vwin = sm + kViFixed + 3 * n + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i <= n; i += kBlock) bstart[i] = block_start[i];
-  for (int i = tid; i < n; i += kBlock) res[i] = 0.0;
+  for (int i = tid; i < n; i += kBlock) {
+    res[i] = 0.0;
+    const VIState *st = D[i].st;
+    stc[i] = make_int2(st->sweeps, st->done);
+  }
   __syncthreads();
+  // a contiguous range of blocks per workgroup, so consecutive blocks share a
+  // problem; the problem index is wave-uniform, so descriptor loads are scalar
   const int64_t total = bstart[n];
-  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-    const int i = batch_problem(bstart, n, g);
-    const BatchVIDesc &d = D[i];
-    if (d.st->done) continue;  // uniform per block
-    const int sweeps = d.st->sweeps;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t g_end = min(total, (int64_t)(blockIdx.x + 1) * per);
+  for (int64_t g = (int64_t)blockIdx.x * per; g < g_end; ++g) {
+    const int i = __builtin_amdgcn_readfirstlane(batch_problem(bstart, n, g));
+    const int2 sd = stc[i];
+    if (sd.y) continue;  // converged (uniform per block)
+    const BatchVIDesc d = load_const(D + i);
+    const VIParams &P = d.P;
     const int64_t blk = g - bstart[i];
-    const int t = (int)(blk / d.P.blocks_per_layer);
-    if (t >= vi_active_layers(d.P.nt, sweeps)) continue;
-    const int c0 = (int)(blk - (int64_t)t * d.P.blocks_per_layer) * d.P.states_per_wg;
-    const bool odd = (sweeps & 1) != 0;
+    const int t = (int)(blk / P.blocks_per_layer);
+    if (t >= vi_active_layers(P.nt, sd.x)) continue;
+    const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
+    const bool odd = (sd.x & 1) != 0;
     const double *vin = odd ? d.v_alt : d.v;
     double *vout = odd ? d.v : d.v_alt;
-    const double m = block_max(vi_block<false>(d.P, vin, vout, nullptr, t, c0, sm, vwin), sm + kViWmax);
+    const double m = block_max(vi_block<false>(P, vin, vout, nullptr, t, c0, sm, vwin), sm + kViWmax);
     if (tid == 0) res[i] = fmax(res[i], m);
   }
   __syncthreads();
@@ -368,17 +380,20 @@ __global__ __launch_bounds__(kBlock) void k_policy_batched(const BatchVIDesc *D,
 {
   extern __shared__ double sm[];
   int64_t *bstart = reinterpret_cast<int64_t *>(sm + kViFixed + n);
-  double *vwin = sm + kViFixed + 2 * n + 1;
+  double *vwin = sm + kViFixed + 3 * n + 1;
   for (int i = threadIdx.x; i <= n; i += kBlock) bstart[i] = block_start[i];
   __syncthreads();
   const int64_t total = bstart[n];
-  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-    const int i = batch_problem(bstart, n, g);
-    const BatchVIDesc &d = D[i];
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t g_end = min(total, (int64_t)(blockIdx.x + 1) * per);
+  for (int64_t g = (int64_t)blockIdx.x * per; g < g_end; ++g) {
+    const int i = __builtin_amdgcn_readfirstlane(batch_problem(bstart, n, g));
+    const BatchVIDesc d = load_const(D + i);
+    const VIParams &P = d.P;
     const int64_t blk = g - bstart[i];
-    const int t = (int)(blk / d.P.blocks_per_layer);
-    const int c0 = (int)(blk - (int64_t)t * d.P.blocks_per_layer) * d.P.states_per_wg;
-    vi_block<true>(d.P, d.v, nullptr, d.pi, t, c0, sm, vwin);
+    const int t = (int)(blk / P.blocks_per_layer);
+    const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
+    vi_block<true>(P, d.v, nullptr, d.pi, t, c0, sm, vwin);
   }
 }
 
@@ -397,7 +412,7 @@ static hipError_t allow_lds(const void *kern, bool &done)
 
 static size_t single_lds(const VIParams &P) { return (size_t)kViFixed * 8 + (size_t)P.win_rows * P.nx * 8; }
 
-static size_t batch_lds(int n, size_t win_bytes) { return ((size_t)kViFixed + 2 * (size_t)n + 2) * 8 + win_bytes; }
+static size_t batch_lds(int n, size_t win_bytes) { return ((size_t)kViFixed + 3 * (size_t)n + 2) * 8 + win_bytes; }
 
 hipError_t launch_vi_init(VIState *st, int n, hipStream_t s)
 {
