@@ -158,7 +158,21 @@ def _served_trace(seconds: float, rate: float, seed: int = 7):
     return arr, reqs
 
 
-def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
+def served_inputs(pl, seconds: float, rate: float):
+    """The trace's requests with their environments resident on the device and
+    their sub-grids sized (outside any timed region)."""
+    from paper_2109_00857_amd import mdp
+
+    arr, reqs = _served_trace(seconds, rate)
+    envs = [pl.upload_env(w) for w, _ in reqs]
+    for (w, _), env in zip(reqs, envs):  # requests arrive with their sub-grid sized
+        if w.problem["sub_hx"] == 0 and w.problem["sub_hy"] == 0:
+            w.problem["sub_hx"], w.problem["sub_hy"] = mdp.mdp_subgrid_auto(pl.ctx, w.problem, env)
+    return arr, reqs, envs
+
+
+def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_share: int = 50,
+               sweeps_per_step: int = 32, sequential: bool = True, trace=None) -> dict:
     """The served trace through the continuous-batching server, then the same trace
     through sequential plain solves (first come, first served, one at a time)."""
     import numpy as np
@@ -167,11 +181,9 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
     from paper_2109_00857_amd import mdp
 
     t_gen = time.perf_counter()
-    arr, reqs = _served_trace(seconds, rate)
-    envs = [pl.upload_env(w) for w, _ in reqs]
-    for (w, _), env in zip(reqs, envs):  # requests arrive with their sub-grid sized
-        if w.problem["sub_hx"] == 0 and w.problem["sub_hy"] == 0:
-            w.problem["sub_hx"], w.problem["sub_hy"] = mdp.mdp_subgrid_auto(pl.ctx, w.problem, env)
+    if trace is None:
+        trace = served_inputs(pl, seconds, rate)
+    arr, reqs, envs = trace
     t_gen = time.perf_counter() - t_gen
     n = len(reqs)
     samples = sum(w.nominal_samples for w, _ in reqs)
@@ -183,15 +195,18 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
                     requests_per_s=n / wall, samples_per_s=samples / wall)
 
     s = torch.cuda.Stream()
-    srv = mdp.Server(pl, pool_bytes=int(pool_gib * (1 << 30)), max_inflight=64, sweeps_per_step=8, stream=s)
+    srv = mdp.Server(pl, pool_bytes=int(pool_gib * (1 << 30)), max_inflight=64, sweeps_per_step=sweeps_per_step,
+                     stream=s, build_share=build_share)
     # warm the server's code paths on the first two requests (results discarded)
     for j in range(min(2, n)):
         srv.submit(-1 - j, reqs[j][0].problem, envs[j], reqs[j][1])
     while srv.step():
         pass
     srv.poll()
-    lat, status = {}, {}
-    i = 0
+    first_step = srv.info()["steps"]  # step numbers continue after the warm-up
+    lat, status, admit = {}, {}, {}
+    step_start = {}  # step number -> host time it started
+    i, n_steps, t_steps = 0, 0, 0.0
     t0 = time.perf_counter()
     while len(lat) < n:
         now = time.perf_counter() - t0
@@ -199,19 +214,30 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
             srv.submit(i, reqs[i][0].problem, envs[i], reqs[i][1])
             i += 1
         if i - len(lat) > 0:
+            ts = time.perf_counter()
+            n_steps += 1
+            step_start[n_steps] = ts - t0
             srv.step()
+            t_steps += time.perf_counter() - ts
         elif i < n:
             time.sleep(max(0.0, arr[i] - (time.perf_counter() - t0)))
         t = time.perf_counter() - t0
         for rec in srv.poll():
             lat[rec["tag"]] = t - arr[rec["tag"]]
             status[rec["tag"]] = rec["status"]
+            admit[rec["tag"]] = step_start.get(rec["admit_step"] - first_step, arr[rec["tag"]]) - arr[rec["tag"]]
     wall_served = time.perf_counter() - t0
     srv.close()
     del srv
     torch.cuda.empty_cache()
     served = stats(lat, wall_served)
     served["all_ok"] = all(v == mdp.MDP_OK for v in status.values())
+    served["steps"] = n_steps
+    served["mean_step_ms"] = 1e3 * t_steps / max(n_steps, 1)
+    served["mean_queue_wait_ms"] = 1e3 * float(np.mean([max(0.0, admit[j]) for j in range(n)]))
+    if not sequential:
+        return dict(requests=n, samples=samples, served=served, build_share=build_share,
+                    sweeps_per_step=sweeps_per_step)
 
     # sequential plain solves of the same trace
     lat2 = {}
@@ -239,6 +265,7 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0) -> dict:
     seq = stats(lat2, wall_seq)
     return dict(trace=f"Poisson {rate}/s for {seconds} s (seed 7): {n} requests, 90% uneven batched-mix, "
                       f"10% paper-shaped, missions uniform", requests=n, samples=samples, generator_s=t_gen,
+                build_share=build_share, sweeps_per_step=sweeps_per_step,
                 served=served, sequential_plain=seq,
                 p50_speedup=seq["p50_ms"] / served["p50_ms"], p99_speedup=seq["p99_ms"] / served["p99_ms"])
 
@@ -254,6 +281,9 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-trace leg")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the served trace")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrival rate (per second)")
+    ap.add_argument("--build-share", type=int, default=50,
+                    help="percent of the GPU's resident workgroups a served build batch may hold")
+    ap.add_argument("--serve-sweeps", type=int, default=32, help="most sweeps per served scheduler step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -403,7 +433,8 @@ def main():
             out["batched"] = {"error": repr(e)}
     if not args.no_served:
         try:
-            out["served"] = served_leg(pl, args.serve_seconds, args.serve_rate)
+            out["served"] = served_leg(pl, args.serve_seconds, args.serve_rate, build_share=args.build_share,
+                                       sweeps_per_step=args.serve_sweeps)
             out["p50_ms_served"] = out["served"]["served"]["p50_ms"]
             out["p99_ms_served"] = out["served"]["served"]["p99_ms"]
         except Exception as e:

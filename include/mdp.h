@@ -227,12 +227,16 @@ mdp_status mdp_batch_destroy(mdp_batch *b);
 /* ------------------------------------------------------------------ serving
  * Continuous batching of planning requests (not in the paper). Requests queue
  * in arrival order; each mdp_server_step
- *   1. admits queued requests in order while a slot is free and the pool holds
- *      the request's footprint (mdp_server_footprint: model with the worst-case
+ *   1. admits queued requests while a slot is free and the pool holds the
+ *      request's footprint (mdp_server_footprint: model with the worst-case
  *      nonzeros rows * min(N_sg, n_real), values, policy, and its share of the
- *      build scratch);
- *   2. builds every newly admitted request in one batched build launch and
- *      gives the unused part of the worst-case reservation back to the pool;
+ *      build scratch); small and large builds have a lane each (a stream, one
+ *      build batch at a time), requests are admitted in arrival order within
+ *      their size class, and a batch holds builds within a factor 4 in cost;
+ *   2. builds every newly admitted request in one batched build, split into
+ *      short launches that the other lane and the sweeps interleave with, and,
+ *      once it has finished, gives the unused part of the worst-case
+ *      reservation back to the pool;
  *   3. runs up to sweeps_per_step synchronous sweeps over every admitted
  *      request in one launch per sweep (requests joined at different sweeps);
  *   4. retires each request that converged (or reached its sweep limit):
@@ -247,9 +251,11 @@ mdp_status mdp_batch_destroy(mdp_batch *b);
 typedef struct mdp_server mdp_server;
 typedef struct mdp_server_config {
   int32_t max_inflight;    /* requests admitted at once, 1..1024                */
-  int32_t sweeps_per_step; /* most sweeps a step enqueues, >= 1                 */
+  int32_t sweeps_per_step; /* most sweeps a step enqueues, 1..256               */
   int32_t max_sweeps;      /* a request retires unconverged after this many     */
-  int32_t pad;
+  int32_t build_share;     /* percent of the resident workgroups a build batch
+                              may hold (1..100; 0 = 100); the rest keeps
+                              sweeping the admitted requests meanwhile          */
   double tol;              /* residual below which a request has converged      */
 } mdp_server_config;
 typedef struct mdp_served {

@@ -7,9 +7,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <deque>
 #include <map>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -651,7 +653,7 @@ const char *batch_layout(int n, const mdp_problem *probs, int64_t pool_entries, 
   };
   L.st = take(sizeof(BuildState) * n);
   L.bstats = take(sizeof(mdp_build_stats) * n);
-  L.ctr = take(4 * kMaxBuildGroups + 8);  // group work counters, staging pool top
+  L.ctr = take(4 * kMaxBuildLaunches + 8);  // group work counters, staging pool top
   L.vst = take(sizeof(VIState) * n);
   L.vstats = take(sizeof(mdp_vi_stats) * n);
   L.wg_res = take(sizeof(double) * (size_t)kBatchViGrid * n);
@@ -769,7 +771,8 @@ struct BuildGroup {
 // group, by descending cost; fill each group's item range and grid.
 hipError_t plan_build_groups(std::vector<std::pair<double, BatchItem>> &items, const std::vector<int> &kmax_of,
                              const std::vector<char> &near_of, const std::vector<size_t> &lds_of,
-                             std::vector<BatchItem> &flat, std::vector<BuildGroup> &groups)
+                             std::vector<BatchItem> &flat, std::vector<BuildGroup> &groups, int share_pct = 100,
+                             std::vector<double> *flat_cost = nullptr)
 {
   const int n = (int)kmax_of.size();
   std::vector<int> gid(n);
@@ -800,6 +803,10 @@ hipError_t plan_build_groups(std::vector<std::pair<double, BatchItem>> &items, c
                    });
   flat.resize(items.size());
   for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].second;
+  if (flat_cost) {
+    flat_cost->resize(items.size());
+    for (size_t k = 0; k < items.size(); ++k) (*flat_cost)[k] = items[k].first;
+  }
   for (size_t k = 0; k < flat.size(); ++k) {
     BuildGroup &G = groups[gid[flat[k].inst]];
     if (G.count == 0) G.first = (int)k;
@@ -808,22 +815,39 @@ hipError_t plan_build_groups(std::vector<std::pair<double, BatchItem>> &items, c
   for (BuildGroup &G : groups) {
     hipError_t e = batch_build_grid(G.kmax, G.near, G.lds, std::max(G.count, 1), &G.grid);
     if (e != hipSuccess) return e;
+    if (share_pct > 0 && share_pct < 100) G.grid = std::max(1, (int)((int64_t)G.grid * share_pct / 100));
   }
   return hipSuccess;
 }
 
-// Enqueue the persistent launches of a batched build (after its init kernel).
+// Enqueue the persistent launches of a batched build (after its init kernel):
+// one per group, or, when item_cost is given, consecutive chunks of at most
+// max_cost each (so that work on other streams can run between them).
 hipError_t enqueue_build_groups(mdp_ctx *ctx, const BatchBuildDesc *D, const BatchItem *d_items,
                                 const std::vector<BuildGroup> &groups, unsigned int *counters, uint64_t *pool,
-                                unsigned long long *pool_top, int64_t pool_cap, hipStream_t s)
+                                unsigned long long *pool_top, int64_t pool_cap, hipStream_t s,
+                                const std::vector<double> *item_cost = nullptr, double max_cost = 0.0)
 {
+  int launch = 0;
   for (size_t g = 0; g < groups.size(); ++g) {
     const BuildGroup &G = groups[g];
-    if (G.count == 0) continue;
-    Timed tm(ctx, MDP_KERNEL_BUILD, s);
-    hipError_t e = launch_batch_build(D, d_items + G.first, G.count, counters + g, pool, pool_top, pool_cap, G.kmax,
-                                      G.near, G.lds, G.grid, s);
-    if (e != hipSuccess) return e;
+    int k = G.first;
+    const int end = G.first + G.count;
+    while (k < end) {
+      int k1 = end;
+      if (item_cost && max_cost > 0.0 && kMaxBuildLaunches - launch > (int)(groups.size() - g)) {
+        double c = 0.0;
+        k1 = k;
+        while (k1 < end && (k1 == k || c + (*item_cost)[k1] <= max_cost)) c += (*item_cost)[k1++];
+      }
+      if (launch == kMaxBuildLaunches - 1) k1 = end;  // the last counter takes the rest
+      Timed tm(ctx, MDP_KERNEL_BUILD, s);
+      hipError_t e = launch_batch_build(D, d_items + k, k1 - k, counters + launch, pool, pool_top, pool_cap, G.kmax,
+                                        G.near, G.lds, std::min(G.grid, k1 - k), s);
+      if (e != hipSuccess) return e;
+      ++launch;
+      k = k1;
+    }
   }
   return hipSuccess;
 }
@@ -993,7 +1017,7 @@ mdp_status mdp_batch_build(mdp_batch *b, void *stream)
   hipStream_t s = (hipStream_t)stream;
   char *sc = b->scratch;
   unsigned int *counter = (unsigned int *)(sc + b->L.ctr);  // one per group
-  unsigned long long *pool_top = (unsigned long long *)(sc + b->L.ctr + 4 * kMaxBuildGroups);
+  unsigned long long *pool_top = (unsigned long long *)(sc + b->L.ctr + 4 * kMaxBuildLaunches);
   uint64_t *pool = (uint64_t *)(sc + b->L.pool);
   hipError_t e;
   if ((e = launch_batch_build_init(b->d_bdesc, b->n, counter, pool_top, s)) != hipSuccess)
@@ -1204,7 +1228,8 @@ struct ServeReq {
   ReqSizes z{};
   Block keep, col, cnt;
   int64_t model_cap = 0;  // col / cnt entries held: worst case until the build is checked
-  int sweeps = 0;         // sweeps enqueued since admission
+  bool cold = false;      // built; v and the sweep state are reset at its first step
+  int sweeps = 0;         // sweeps enqueued since its first step
   int limit = 0;   // sweeps after which the request retires in any case
   mdp_served res{};
   // addresses inside the pool (valid while admitted)
@@ -1219,37 +1244,93 @@ struct ServeReq {
 
 }  // namespace
 
+// Pinned host staging of one kind of upload or download; it is rewritten only
+// after the device work that used it last has completed.
+struct Pinned {
+  void *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes)
+  {
+    if (bytes <= n) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipHostMalloc(&p, std::max<size_t>(bytes, 64), hipHostMallocDefault);
+    if (e == hipSuccess) n = std::max<size_t>(bytes, 64);
+    return e;
+  }
+  template <typename T>
+  T *as() const
+  {
+    return (T *)p;
+  }
+  ~Pinned()
+  {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// A build lane: one build batch at a time on a stream of its own. Small and
+// large requests use different lanes, so a small build never waits for a
+// large one (each large build is split into short launches that the small
+// lane's and the sweeps' kernels interleave with).
+struct BuildLane {
+  hipStream_t stream = nullptr;
+  hipEvent_t event = nullptr;       // end of the batch in flight
+  std::vector<ServeReq *> building; // the batch in flight
+  Block blk;                        // its scratch and staging block
+  BatchBuildDesc *d_bdesc = nullptr;
+  float *d_tabs = nullptr;
+  BatchItem *d_items = nullptr;
+  size_t items_cap = 0;
+  Pinned h_bdesc, h_items, h_tabs, h_bstat;
+};
+
+constexpr int kServeLanes = 2;  // 0: small builds, 1: large builds
+
 struct mdp_server {
   mdp_ctx *ctx = nullptr;
   mdp_server_config cfg{};
   char *pool = nullptr;
   size_t pool_bytes = 0;
   RangeAlloc alloc;
-  std::deque<ServeReq *> queue;
-  std::vector<ServeReq *> running;
-  std::vector<mdp_served> done;
+  std::deque<ServeReq *> queue;     // submitted, not admitted
+  BuildLane lane[kServeLanes];
+  std::vector<ServeReq *> running;  // built; swept on the caller's stream
+  std::vector<mdp_served> done;     // completion records not yet polled
   int64_t step_no = 0;
   // device tables, sized for cfg.max_inflight problems
-  BatchBuildDesc *d_bdesc = nullptr;
   BatchVIDesc *d_vrun = nullptr, *d_vret = nullptr;
-  int64_t *d_bs_run = nullptr, *d_bs_ret = nullptr;
+  int64_t *d_bs_ret = nullptr;
   int64_t *d_bs_sweeps = nullptr;  // [sweeps_per_step][max_inflight + 1]
   double *d_wg_res = nullptr;
   mdp_vi_stats *d_vstat = nullptr;
-  float *d_tabs = nullptr;
-  BatchItem *d_items = nullptr;
-  size_t items_cap = 0;
-  unsigned int *d_ctr = nullptr;  // work counter + staging pool top
+  // pinned staging
+  Pinned h_vrun, h_tables, h_vstat, h_vret, h_bsret, h_fstat, h_vstart;
+  size_t n_building() const
+  {
+    size_t k = 0;
+    for (const BuildLane &L : lane) k += L.building.size();
+    return k;
+  }
 };
 
 namespace {
 
 void serve_free_all(mdp_server *S)
 {
+  for (BuildLane &L : S->lane) {
+    if (L.event && !L.building.empty()) (void)hipEventSynchronize(L.event);
+    for (ServeReq *r : L.building) delete r;
+    void *bufs[] = {L.d_bdesc, L.d_tabs, L.d_items};
+    for (void *p : bufs)
+      if (p) (void)hipFree(p);
+    if (L.event) (void)hipEventDestroy(L.event);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+  }
   for (ServeReq *r : S->queue) delete r;
   for (ServeReq *r : S->running) delete r;
-  void *bufs[] = {S->d_bdesc, S->d_vrun, S->d_vret, S->d_bs_run, S->d_bs_ret, S->d_bs_sweeps,
-                  S->d_wg_res, S->d_vstat, S->d_tabs, S->d_items, S->d_ctr};
+  void *bufs[] = {S->d_vrun, S->d_vret, S->d_bs_ret, S->d_bs_sweeps, S->d_wg_res, S->d_vstat};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete S;
@@ -1307,64 +1388,87 @@ void unreserve(mdp_server *S, ServeReq *r)
   give(S->alloc, r->keep);
 }
 
-mdp_model req_model(const ServeReq *r)
+mdp_model req_model(const ServeReq *r) { return mdp_model{r->row_ptr, r->colp, r->cntp, r->reward, r->model_cap}; }
+
+constexpr size_t kServeCtrBytes = 4 * kMaxBuildLaunches + 8;  // launch work counters, staging pool top
+// Work of one launch of a served build, in the cost unit of the work list
+// (landings plus a quarter landing per mode term): about 2 ms on an MI355X,
+// so the sweeps of admitted requests interleave with long builds.
+constexpr double kServeChunkCost = 6e9;
+// A build batch takes the requests behind the first one only while their
+// build cost stays within this factor of the first one's.
+constexpr double kServeCostRatio = 4.0;
+// A step sweeps the requests whose remaining work is within this factor of
+// the smallest remaining work.
+constexpr double kServeWorkRatio = 4.0;
+// Requests above this build cost use the large-build lane (a paper-shaped
+// 100 x 100 x 120 request with 5000 realizations and 16 headings is ~1.1e11).
+constexpr double kServeLargeCost = 3e10;
+
+double build_cost(const ServeReq *r)
 {
-  return mdp_model{r->row_ptr, r->colp, r->cntp, r->reward, r->model_cap};
+  return (double)r->z.rows * r->p.n_real * (1.0 + 0.25 * r->p.n_modes / std::max(r->pl.na, 1));
 }
 
 size_t build_block_bytes(const std::vector<ServeReq *> &fresh)
 {
-  size_t b = align_up(4 * kMaxBuildGroups + 8);  // group work counters and staging pool top
+  size_t b = align_up(kServeCtrBytes) + align_up(sizeof(BuildState) * fresh.size()) +
+             align_up(sizeof(mdp_build_stats) * fresh.size());
   for (const ServeReq *r : fresh) b += r->z.build;
   return b;
 }
 
-// Upload descriptors and enqueue the batched build of the freshly admitted
-// requests; build statistics land in bstats (device, one per request).
-mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char *blk, hipStream_t s,
-                       mdp_build_stats **bstats_out)
+// Enqueue the batched build of the requests in L.building on the lane's
+// stream: descriptors through pinned staging, the persistent launches (in
+// short chunks), scan, copy and statistics (copied to pinned memory), then the
+// batch's event.
+mdp_status serve_build(mdp_server *S, BuildLane &L, char *blk)
 {
+  const std::vector<ServeReq *> &fresh = L.building;
   const int n = (int)fresh.size();
-  std::vector<BatchBuildDesc> bd(n);
-  std::vector<float> tabs((size_t)n * 2 * kMaxA, 0.0f);
+  hipStream_t s = L.stream;
+  hipError_t e;
+  if ((e = L.h_bdesc.ensure(sizeof(BatchBuildDesc) * n)) != hipSuccess ||
+      (e = L.h_tabs.ensure(sizeof(float) * 2 * kMaxA * n)) != hipSuccess ||
+      (e = L.h_bstat.ensure(sizeof(mdp_build_stats) * n)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve staging");
+  BatchBuildDesc *bd = L.h_bdesc.as<BatchBuildDesc>();
+  float *tabs = L.h_tabs.as<float>();
+  memset(tabs, 0, sizeof(float) * 2 * kMaxA * n);
   std::vector<std::pair<double, BatchItem>> items;
-  size_t o = align_up(4 * kMaxBuildGroups + 8);
-  unsigned int *counter = (unsigned int *)blk;  // one per group
-  unsigned long long *pool_top = (unsigned long long *)(blk + 4 * kMaxBuildGroups);
-  // per-request scratch first, staging pool entries of every request last
+  unsigned int *counter = (unsigned int *)blk;
+  unsigned long long *pool_top = (unsigned long long *)(blk + 4 * kMaxBuildLaunches);
+  size_t o = align_up(kServeCtrBytes);
+  BuildState *st = (BuildState *)(blk + o);
+  o += align_up(sizeof(BuildState) * n);
+  mdp_build_stats *bstats = (mdp_build_stats *)(blk + o);
+  o += align_up(sizeof(mdp_build_stats) * n);
   std::vector<BuildScratch> B(n);
-  mdp_build_stats *bstats = nullptr;
   int64_t pool_cap = 0;
+  for (int i = 0; i < n; ++i) {
+    const ServeReq *r = fresh[i];
+    const size_t items_i = (size_t)r->p.nt * r->pl.tiles_per_layer;
+    B[i].st = st + i;
+    B[i].row_nnz = (uint32_t *)(blk + o);
+    o += align_up(4 * (size_t)r->z.rows);
+    B[i].row_off = (uint32_t *)(blk + o);
+    o += align_up(4 * (size_t)r->z.rows);
+    B[i].item_total = (uint32_t *)(blk + o);
+    o += align_up(4 * items_i);
+    B[i].item_base = (int64_t *)(blk + o);
+    o += align_up(8 * items_i);
+    B[i].item_off = (int64_t *)(blk + o);
+    o += align_up(8 * items_i);
+    pool_cap += r->z.cap;
+  }
+  uint64_t *pool = (uint64_t *)(blk + o);
   std::vector<int> kmax_of(n);
   std::vector<char> near_of(n);
   std::vector<size_t> lds_of(n);
-  {
-    BuildState *st = (BuildState *)(blk + o);
-    o += align_up(sizeof(BuildState) * n);
-    bstats = (mdp_build_stats *)(blk + o);
-    o += align_up(sizeof(mdp_build_stats) * n);
-    for (int i = 0; i < n; ++i) {
-      const ServeReq *r = fresh[i];
-      const size_t items_i = (size_t)r->p.nt * r->pl.tiles_per_layer;
-      B[i].st = st + i;
-      B[i].row_nnz = (uint32_t *)(blk + o);
-      o += align_up(4 * (size_t)r->z.rows);
-      B[i].row_off = (uint32_t *)(blk + o);
-      o += align_up(4 * (size_t)r->z.rows);
-      B[i].item_total = (uint32_t *)(blk + o);
-      o += align_up(4 * items_i);
-      B[i].item_base = (int64_t *)(blk + o);
-      o += align_up(8 * items_i);
-      B[i].item_off = (int64_t *)(blk + o);
-      o += align_up(8 * items_i);
-      pool_cap += r->z.cap;
-    }
-  }
-  uint64_t *pool = (uint64_t *)(blk + o);
   for (int i = 0; i < n; ++i) {
     ServeReq *r = fresh[i];
     const mdp_model M = req_model(r);
-    if (const char *m = batch_build_desc(i, &r->p, &r->env, M, r->pl, B[i], S->d_tabs + (size_t)i * 2 * kMaxA,
+    if (const char *m = batch_build_desc(i, &r->p, &r->env, M, r->pl, B[i], L.d_tabs + (size_t)i * 2 * kMaxA,
                                          &tabs[(size_t)i * 2 * kMaxA], bd[i], items)) {
       set_err(S->ctx, "request %lld: %s", (long long)r->tag, m);
       return MDP_E_INVALID;
@@ -1375,64 +1479,126 @@ mdp_status serve_build(mdp_server *S, const std::vector<ServeReq *> &fresh, char
   }
   std::vector<BatchItem> flat;
   std::vector<BuildGroup> groups;
-  hipError_t e;
-  if ((e = plan_build_groups(items, kmax_of, near_of, lds_of, flat, groups)) != hipSuccess)
+  std::vector<double> cost;
+  if ((e = plan_build_groups(items, kmax_of, near_of, lds_of, flat, groups, S->cfg.build_share, &cost)) !=
+      hipSuccess)
     return hip_fail(S->ctx, e, "serve occupancy");
-  if (flat.size() > S->items_cap) {
-    if (S->d_items) (void)hipFree(S->d_items);
-    S->d_items = nullptr;
-    S->items_cap = 0;
-    if ((e = hipMalloc((void **)&S->d_items, sizeof(BatchItem) * flat.size())) != hipSuccess)
+  if (flat.size() > L.items_cap) {
+    if (L.d_items) (void)hipFree(L.d_items);
+    L.d_items = nullptr;
+    L.items_cap = 0;
+    if ((e = hipMalloc((void **)&L.d_items, sizeof(BatchItem) * flat.size())) != hipSuccess)
       return hip_fail(S->ctx, e, "serve items");
-    S->items_cap = flat.size();
+    L.items_cap = flat.size();
   }
-  if ((e = hipMemcpyAsync(S->d_bdesc, bd.data(), sizeof(BatchBuildDesc) * n, hipMemcpyHostToDevice, s)) !=
+  if ((e = L.h_items.ensure(sizeof(BatchItem) * flat.size())) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve staging");
+  memcpy(L.h_items.p, flat.data(), sizeof(BatchItem) * flat.size());
+  if ((e = hipMemcpyAsync(L.d_bdesc, bd, sizeof(BatchBuildDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(L.d_tabs, tabs, sizeof(float) * 2 * kMaxA * n, hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
-      (e = hipMemcpyAsync(S->d_tabs, tabs.data(), sizeof(float) * tabs.size(), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(S->d_items, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, s)) !=
+      (e = hipMemcpyAsync(L.d_items, L.h_items.p, sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, s)) !=
           hipSuccess)
     return hip_fail(S->ctx, e, "serve descriptors");
-  // pageable sources: make sure the copies have read them before they go away
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(S->ctx, e, "serve sync");
-  if ((e = launch_batch_build_init(S->d_bdesc, n, counter, pool_top, s)) != hipSuccess)
+  if ((e = launch_batch_build_init(L.d_bdesc, n, counter, pool_top, s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve build init");
-  if ((e = enqueue_build_groups(S->ctx, S->d_bdesc, S->d_items, groups, counter, pool, pool_top, pool_cap, s)) !=
-      hipSuccess)
+  if ((e = enqueue_build_groups(S->ctx, L.d_bdesc, L.d_items, groups, counter, pool, pool_top, pool_cap, s, &cost,
+                                 kServeChunkCost)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve build");
-  if ((e = launch_batch_scan(S->d_bdesc, n, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve scan");
+  if ((e = launch_batch_scan(L.d_bdesc, n, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve scan");
   {
     Timed tm(S->ctx, MDP_KERNEL_COPY, s);
-    if ((e = launch_batch_copy(S->d_bdesc, S->d_items, (int)flat.size(), pool, s)) != hipSuccess)
+    if ((e = launch_batch_copy(L.d_bdesc, L.d_items, (int)flat.size(), pool, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve copy");
   }
-  if ((e = launch_batch_finalize(S->d_bdesc, n, bstats, s)) != hipSuccess)
+  if ((e = launch_batch_finalize(L.d_bdesc, n, bstats, s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve finalize");
-  *bstats_out = bstats;
+  if ((e = hipMemcpyAsync(L.h_bstat.p, bstats, sizeof(mdp_build_stats) * n, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipEventRecord(L.event, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve build end");
   return MDP_OK;
 }
 
-// Upload the solve descriptors of reqs into D / bstart (device).
-mdp_status upload_vi(mdp_server *S, const std::vector<ServeReq *> &reqs, BatchVIDesc *D, int64_t *bstart,
-                     size_t *win_bytes, hipStream_t s, std::vector<BatchVIDesc> *desc_out = nullptr)
+// The build batch has finished: record its statistics, give back the unused
+// worst-case reservations and the build block, and let the requests join the
+// sweeps (cold start at their first step).
+void serve_join(mdp_server *S, BuildLane &L)
 {
-  const int n = (int)reqs.size();
-  std::vector<BatchVIDesc> local;
-  std::vector<BatchVIDesc> &vd = desc_out ? *desc_out : local;
-  vd.resize(n);
-  std::vector<int64_t> bs(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
+  const mdp_build_stats *hb = L.h_bstat.as<mdp_build_stats>();
+  for (size_t i = 0; i < L.building.size(); ++i) {
+    ServeReq *r = L.building[i];
+    r->res.nnz = hb[i].nnz;
+    r->res.samples = hb[i].samples;
+    r->res.build_status = hb[i].status;
+    if (hb[i].status == MDP_OK) {
+      S->alloc.shrink(r->col.off, r->col.len, 4 * (size_t)hb[i].nnz);
+      S->alloc.shrink(r->cnt.off, r->cnt.len, 2 * (size_t)hb[i].nnz);
+      r->col.len = align_up(std::max<size_t>(4 * (size_t)hb[i].nnz, 1));
+      r->cnt.len = align_up(std::max<size_t>(2 * (size_t)hb[i].nnz, 1));
+      r->model_cap = hb[i].nnz;
+    }
+    r->cold = true;
+    S->running.push_back(r);
+  }
+  L.building.clear();
+  give(S->alloc, L.blk);
+}
+
+// Lane of a request: large builds (paper-shaped and above) go to lane 1.
+int lane_of(const ServeReq *r) { return build_cost(r) > kServeLargeCost ? 1 : 0; }
+
+// Admit queued requests of lane li's size class, in order, into a new build
+// batch while slots and pool space last, and enqueue its build.
+mdp_status serve_admit(mdp_server *S, int li)
+{
+  BuildLane &L = S->lane[li];
+  std::vector<ServeReq *> &fresh = L.building;
+  Block &bblk = L.blk;
+  for (auto it = S->queue.begin(); it != S->queue.end();) {
+    if ((int)(S->running.size() + S->n_building()) >= S->cfg.max_inflight) break;
+    ServeReq *r = *it;
+    if (lane_of(r) != li) {
+      ++it;
+      continue;
+    }
+    if (!fresh.empty()) {  // keep a batch's builds within a factor of each other
+      const double c0 = build_cost(fresh.front()), c = build_cost(r);
+      if (c > kServeCostRatio * c0 || c0 > kServeCostRatio * c) break;
+    }
+    const size_t prev_len = bblk.live ? bblk.len : 0;
+    give(S->alloc, bblk);
+    bool ok = reserve(S, r);
+    if (ok) {
+      fresh.push_back(r);
+      ok = take(S->alloc, bblk, build_block_bytes(fresh));
+      if (!ok) {
+        fresh.pop_back();
+        unreserve(S, r);
+      }
+    }
+    if (!ok) {
+      if (prev_len && !take(S->alloc, bblk, prev_len)) {  // the range just freed
+        set_err(S->ctx, "serve pool bookkeeping");
+        return MDP_E_HIP;
+      }
+      break;
+    }
+    r->res.admit_step = S->step_no;
+    it = S->queue.erase(it);
+  }
+  if (fresh.empty()) return MDP_OK;
+  return serve_build(S, L, S->pool + bblk.off);
+}
+
+// Descriptors of reqs into pinned staging vd (returns the widest v window).
+size_t vi_descs(const std::vector<ServeReq *> &reqs, BatchVIDesc *vd)
+{
+  for (size_t i = 0; i < reqs.size(); ++i) {
     ServeReq *r = reqs[i];
     batch_vi_desc(&r->p, req_model(r), r->pl, r->mission, r->v, r->v_alt, r->pi, r->st, vd[i]);
-    bs[i + 1] = bs[i] + vd[i].P.n_blocks;
   }
-  *win_bytes = batch_win_bytes(vd.data(), n);
-  hipError_t e;
-  if ((e = hipMemcpyAsync(D, vd.data(), sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(bstart, bs.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve solve descriptors");
-  return MDP_OK;
+  return batch_win_bytes(vd, (int)reqs.size());
 }
 
 }  // namespace
@@ -1445,7 +1611,8 @@ mdp_status mdp_server_footprint(const mdp_problem *p, size_t *bytes)
   Plan pl;
   if (make_plan(p, pl)) return MDP_E_INVALID;
   const ReqSizes z = req_sizes(p, pl);
-  *bytes = z.keep + z.col + z.cnt + z.build + align_up(4 * kMaxBuildGroups + 8);
+  *bytes = z.keep + z.col + z.cnt + z.build + align_up(kServeCtrBytes) + align_up(sizeof(BuildState)) +
+           align_up(sizeof(mdp_build_stats));
   return MDP_OK;
 }
 
@@ -1455,8 +1622,9 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
   if (!ctx || !cfg || !out) return MDP_E_INVALID;
   *out = nullptr;
   if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxBatch || cfg->sweeps_per_step < 1 ||
-      cfg->sweeps_per_step > 256 || cfg->max_sweeps < 1) {
-    set_err(ctx, "max_inflight must be in [1, 1024], sweeps_per_step in [1, 256], max_sweeps >= 1");
+      cfg->sweeps_per_step > 256 || cfg->max_sweeps < 1 || cfg->build_share < 0 || cfg->build_share > 100) {
+    set_err(ctx, "max_inflight must be in [1, 1024], sweeps_per_step in [1, 256], max_sweeps >= 1, "
+                 "build_share in [0, 100]");
     return MDP_E_INVALID;
   }
   if (!is_device_ptr(pool) || pool_bytes < kAlign) {
@@ -1470,16 +1638,29 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
   S->pool_bytes = pool_bytes / kAlign * kAlign;
   S->alloc.reset(S->pool_bytes);
   const size_t n = (size_t)cfg->max_inflight;
+  const size_t nt = (size_t)cfg->sweeps_per_step;
   hipError_t e;
-  if ((e = hipMalloc((void **)&S->d_bdesc, sizeof(BatchBuildDesc) * n)) != hipSuccess ||
-      (e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
+  for (BuildLane &L : S->lane)
+    if ((e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&L.event, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipMalloc((void **)&L.d_bdesc, sizeof(BatchBuildDesc) * n)) != hipSuccess ||
+        (e = hipMalloc((void **)&L.d_tabs, sizeof(float) * 2 * kMaxA * n)) != hipSuccess) {
+      serve_free_all(S);
+      return hip_fail(ctx, e, "server build lanes");
+    }
+  if ((e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vret, sizeof(BatchVIDesc) * n)) != hipSuccess ||
-      (e = hipMalloc((void **)&S->d_bs_run, sizeof(int64_t) * (n + 1))) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_bs_ret, sizeof(int64_t) * (n + 1))) != hipSuccess ||
-      (e = hipMalloc((void **)&S->d_bs_sweeps, sizeof(int64_t) * (n + 1) * cfg->sweeps_per_step)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_bs_sweeps, sizeof(int64_t) * (n + 1) * nt)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_wg_res, sizeof(double) * kBatchViGrid * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vstat, sizeof(mdp_vi_stats) * n)) != hipSuccess ||
-      (e = hipMalloc((void **)&S->d_tabs, sizeof(float) * 2 * kMaxA * n)) != hipSuccess) {
+      (e = S->h_vrun.ensure(sizeof(BatchVIDesc) * n)) != hipSuccess ||
+      (e = S->h_tables.ensure(sizeof(int64_t) * (n + 1) * nt)) != hipSuccess ||
+      (e = S->h_vstat.ensure(sizeof(mdp_vi_stats) * n)) != hipSuccess ||
+      (e = S->h_vret.ensure(sizeof(BatchVIDesc) * n)) != hipSuccess ||
+      (e = S->h_bsret.ensure(sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = S->h_fstat.ensure(sizeof(mdp_vi_stats) * n)) != hipSuccess ||
+      (e = S->h_vstart.ensure(sizeof(double) * n)) != hipSuccess) {
     serve_free_all(S);
     return hip_fail(ctx, e, "server tables");
   }
@@ -1514,7 +1695,9 @@ mdp_status mdp_server_submit(mdp_server *S, const mdp_problem *p, const mdp_env 
     return MDP_E_INVALID;
   }
   r->z = req_sizes(&r->p, r->pl);
-  if (r->z.keep + r->z.col + r->z.cnt + r->z.build + align_up(4 * kMaxBuildGroups + 8) > S->pool_bytes) {
+  size_t need = 0;
+  (void)mdp_server_footprint(&r->p, &need);
+  if (need > S->pool_bytes) {
     set_err(S->ctx, "request %lld needs more than the whole pool", (long long)tag);
     delete r;
     return MDP_E_CAPACITY;
@@ -1533,121 +1716,131 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   hipError_t e;
   mdp_status rc;
   ++S->step_no;
-  // ---- admission (FIFO): model blocks of each request plus one build block
-  // for all requests admitted in this step
-  std::vector<ServeReq *> fresh;
-  Block bblk;
-  while (!S->queue.empty() && (int)(S->running.size() + fresh.size()) < S->cfg.max_inflight) {
-    ServeReq *r = S->queue.front();
-    const size_t prev_len = bblk.len;
-    give(S->alloc, bblk);
-    bool ok = reserve(S, r);
-    if (ok) {
-      fresh.push_back(r);
-      ok = take(S->alloc, bblk, build_block_bytes(fresh));
-      if (!ok) {
-        fresh.pop_back();
-        unreserve(S, r);
+  // ---- finished build batches join the sweeps; idle lanes admit new batches
+  auto poll_lanes = [&](bool wait) -> mdp_status {
+    for (;;) {
+      bool joined = false, busy = false;
+      for (BuildLane &L : S->lane) {
+        if (L.building.empty()) continue;
+        hipError_t q = hipEventQuery(L.event);
+        if (q == hipSuccess) {
+          serve_join(S, L);
+          joined = true;
+        } else if (q == hipErrorNotReady) {
+          busy = true;
+        } else {
+          return hip_fail(S->ctx, q, "serve build");
+        }
       }
+      if (joined || !busy || !wait) return MDP_OK;
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
-    if (!ok) {
-      if (prev_len && !take(S->alloc, bblk, prev_len)) {  // the range just freed
-        set_err(S->ctx, "serve pool bookkeeping");
-        return MDP_E_HIP;
+  };
+  auto admit_idle = [&]() -> mdp_status {
+    for (int li = 0; li < kServeLanes; ++li)
+      if (S->lane[li].building.empty() && !S->queue.empty()) {
+        mdp_status r2 = serve_admit(S, li);
+        if (r2 != MDP_OK) return r2;
       }
-      break;
+    return MDP_OK;
+  };
+  if ((rc = poll_lanes(false)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
+  if (S->running.empty() && S->n_building() > 0) {  // nothing to sweep until a build ends
+    if ((rc = poll_lanes(true)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
+  }
+  if (S->running.empty()) {
+    if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building());
+    return MDP_OK;
+  }
+  // ---- sweeps, shortest remaining work first: this step sweeps the built
+  // requests whose remaining work (rows times sweeps still to run) is within
+  // kServeWorkRatio of the smallest; the others wait (their state is untouched)
+  std::vector<ServeReq *> sweep, paused;
+  {
+    double wmin = 0.0;
+    bool first = true;
+    for (ServeReq *r : S->running) {
+      const double w = (double)r->z.rows * (r->limit - r->sweeps);
+      if (first || w < wmin) wmin = w;
+      first = false;
     }
-    r->res.admit_step = S->step_no;
-    S->queue.pop_front();
+    for (ServeReq *r : S->running)
+      ((double)r->z.rows * (r->limit - r->sweeps) <= kServeWorkRatio * wmin ? sweep : paused).push_back(r);
   }
-  mdp_build_stats *d_bstats = nullptr;
-  if (!fresh.empty()) {
-    if ((rc = serve_build(S, fresh, S->pool + bblk.off, s, &d_bstats)) != MDP_OK) return rc;
-  }
-  // ---- solve: every admitted request, fresh ones last (cold start)
-  const int n_old = (int)S->running.size();
-  S->running.insert(S->running.end(), fresh.begin(), fresh.end());
+  S->running = sweep;
+  struct KeepPaused {  // paused requests return to the running set on every exit
+    std::vector<ServeReq *> &run, &paused;
+    bool armed = true;
+    ~KeepPaused()
+    {
+      if (armed) run.insert(run.end(), paused.begin(), paused.end());
+    }
+  } keep_paused{S->running, paused};
   const int n_run = (int)S->running.size();
-  std::vector<mdp_build_stats> hb(fresh.size());
-  if (n_run > 0) {
-    size_t win = 0;
-    std::vector<BatchVIDesc> vd;
-    if ((rc = upload_vi(S, S->running, S->d_vrun, S->d_bs_run, &win, s, &vd)) != MDP_OK) return rc;
-    if ((e = launch_vi_reset_batched(S->d_vrun + n_old, n_run - n_old, s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve reset");
-    int k = S->cfg.sweeps_per_step;
-    for (ServeReq *r : S->running) k = std::min(k, r->limit - r->sweeps);
-    k = std::max(k, 0);
-    std::vector<int> done_sweeps(n_run);
-    for (int i = 0; i < n_run; ++i) done_sweeps[i] = S->running[i]->sweeps;
-    std::vector<int64_t> tabs;
-    active_block_tables(vd.data(), done_sweeps.data(), n_run, std::max(k, 1), tabs);
-    if ((e = hipMemcpyAsync(S->d_bs_sweeps, tabs.data(), sizeof(int64_t) * tabs.size(), hipMemcpyHostToDevice, s)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve sweep tables");
-    for (int j = 0; j < k; ++j) {
-      Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
-      if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_sweeps + (size_t)j * (n_run + 1), S->d_wg_res,
-                                       kBatchViGrid, win, s)) != hipSuccess)
-        return hip_fail(S->ctx, e, "serve sweep");
-      if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
-        return hip_fail(S->ctx, e, "serve close");
-    }
-    for (ServeReq *r : S->running) r->sweeps += k;
-    if ((e = launch_vi_status_batched(S->d_vrun, n_run, S->d_vstat, s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve status");
+  BatchVIDesc *vd = S->h_vrun.as<BatchVIDesc>();
+  const size_t win = vi_descs(S->running, vd);
+  if ((e = hipMemcpyAsync(S->d_vrun, vd, sizeof(BatchVIDesc) * n_run, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve descriptors");
+  for (int i = 0; i < n_run; ++i) {
+    ServeReq *r = S->running[i];
+    if (!r->cold) continue;
+    if ((e = launch_vi_reset_batched(S->d_vrun + i, 1, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve reset");
+    r->cold = false;
   }
-  std::vector<mdp_vi_stats> hv(n_run);
-  if (!fresh.empty() &&
-      (e = hipMemcpyAsync(hb.data(), d_bstats, sizeof(mdp_build_stats) * fresh.size(), hipMemcpyDeviceToHost, s)) !=
-          hipSuccess)
-    return hip_fail(S->ctx, e, "serve build stats");
-  if (n_run > 0 &&
-      (e = hipMemcpyAsync(hv.data(), S->d_vstat, sizeof(mdp_vi_stats) * n_run, hipMemcpyDeviceToHost, s)) !=
-          hipSuccess)
+  int k = S->cfg.sweeps_per_step;
+  for (ServeReq *r : S->running) k = std::min(k, r->limit - r->sweeps);
+  k = std::max(k, 1);
+  std::vector<int> behind(n_run);
+  for (int i = 0; i < n_run; ++i) behind[i] = S->running[i]->sweeps;
+  std::vector<int64_t> tabs;
+  active_block_tables(vd, behind.data(), n_run, k, tabs);
+  memcpy(S->h_tables.p, tabs.data(), sizeof(int64_t) * tabs.size());
+  if ((e = hipMemcpyAsync(S->d_bs_sweeps, S->h_tables.p, sizeof(int64_t) * tabs.size(), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return hip_fail(S->ctx, e, "serve sweep tables");
+  for (int j = 0; j < k; ++j) {
+    Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
+    if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_sweeps + (size_t)j * (n_run + 1), S->d_wg_res,
+                                     kBatchViGrid, win, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve sweep");
+    if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve close");
+  }
+  for (ServeReq *r : S->running) r->sweeps += k;
+  mdp_vi_stats *hv = S->h_vstat.as<mdp_vi_stats>();
+  if ((e = launch_vi_status_batched(S->d_vrun, n_run, S->d_vstat, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(hv, S->d_vstat, sizeof(mdp_vi_stats) * n_run, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve vi stats");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(S->ctx, e, "serve sync");
-  give(S->alloc, bblk);
-  // ---- build results: shrink each model to its nonzeros
-  for (size_t i = 0; i < fresh.size(); ++i) {
-    ServeReq *r = fresh[i];
-    r->res.nnz = hb[i].nnz;
-    r->res.samples = hb[i].samples;
-    r->res.build_status = hb[i].status;
-    if (hb[i].status == MDP_OK) {
-      S->alloc.shrink(r->col.off, r->col.len, 4 * (size_t)hb[i].nnz);
-      S->alloc.shrink(r->cnt.off, r->cnt.len, 2 * (size_t)hb[i].nnz);
-      r->col.len = align_up(std::max<size_t>(4 * (size_t)hb[i].nnz, 1));
-      r->cnt.len = align_up(std::max<size_t>(2 * (size_t)hb[i].nnz, 1));
-      r->model_cap = hb[i].nnz;
-    }
-  }
   // ---- retire converged requests (and failed builds)
   std::vector<ServeReq *> ret, keep;
   for (int i = 0; i < n_run; ++i) {
     ServeReq *r = S->running[i];
     r->res.sweeps = hv[i].sweeps;
     r->res.residual = hv[i].residual;
-    const bool failed = r->res.build_status != MDP_OK;
-    if (failed || hv[i].status == MDP_OK || r->sweeps >= r->limit)
+    if (r->res.build_status != MDP_OK || hv[i].status == MDP_OK || r->sweeps >= r->limit)
       ret.push_back(r);
     else
       keep.push_back(r);
   }
   if (!ret.empty()) {
     const int n = (int)ret.size();
-    size_t win = 0;
-    if ((rc = upload_vi(S, ret, S->d_vret, S->d_bs_ret, &win, s)) != MDP_OK) return rc;
-    if ((e = launch_vi_finish_batched(S->d_vret, n, S->d_vstat, s)) != hipSuccess)
+    BatchVIDesc *rd = S->h_vret.as<BatchVIDesc>();
+    const size_t rwin = vi_descs(ret, rd);
+    int64_t *bs = S->h_bsret.as<int64_t>();
+    bs[0] = 0;
+    for (int i = 0; i < n; ++i) bs[i + 1] = bs[i] + rd[i].P.n_blocks;
+    if ((e = hipMemcpyAsync(S->d_vret, rd, sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(S->d_bs_ret, bs, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_vi_finish_batched(S->d_vret, n, S->d_vstat, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve finish");
     {
       Timed tm(S->ctx, MDP_KERNEL_POLICY, s);
-      if ((e = launch_policy_batched(S->d_vret, n, S->d_bs_ret, kBatchViGrid, win, s)) != hipSuccess)
+      if ((e = launch_policy_batched(S->d_vret, n, S->d_bs_ret, kBatchViGrid, rwin, s)) != hipSuccess)
         return hip_fail(S->ctx, e, "serve policy");
     }
-    std::vector<mdp_vi_stats> hf(n);
-    std::vector<double> vstart(n, 0.0);
+    double *vstart = S->h_vstart.as<double>();
+    mdp_vi_stats *hf = S->h_fstat.as<mdp_vi_stats>();
     for (int i = 0; i < n; ++i) {
       ServeReq *r = ret[i];
       const size_t ns = (size_t)r->z.ns;
@@ -1657,8 +1850,7 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
           (r->h_v && (e = hipMemcpyAsync(r->h_v, r->v, 8 * ns, hipMemcpyDeviceToHost, s)) != hipSuccess))
         return hip_fail(S->ctx, e, "serve results");
     }
-    if ((e = hipMemcpyAsync(hf.data(), S->d_vstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) !=
-            hipSuccess ||
+    if ((e = hipMemcpyAsync(hf, S->d_vstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve retire");
     for (int i = 0; i < n; ++i) {
@@ -1673,8 +1865,10 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
       delete r;
     }
   }
+  keep.insert(keep.end(), paused.begin(), paused.end());
+  keep_paused.armed = false;
   S->running.swap(keep);
-  if (n_active) *n_active = (int32_t)(S->queue.size() + S->running.size());
+  if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building() + S->running.size());
   return MDP_OK;
 }
 
@@ -1692,7 +1886,7 @@ mdp_status mdp_server_info(mdp_server *S, mdp_server_state *out)
 {
   if (!S || !out) return MDP_E_INVALID;
   out->queued = (int32_t)S->queue.size();
-  out->in_flight = (int32_t)S->running.size();
+  out->in_flight = (int32_t)(S->n_building() + S->running.size());
   out->completed = (int32_t)S->done.size();
   out->pad = 0;
   out->pool_used = (int64_t)S->alloc.used();

@@ -608,7 +608,7 @@ __global__ void k_batch_build_init(BatchBuildDesc *D, int n, unsigned int *count
                                    unsigned long long *pool_top)
 {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kMaxBuildGroups) counter[i] = 0u;
+  if (i < kMaxBuildLaunches) counter[i] = 0u;
   if (i == 0) *pool_top = 0ull;
   if (i < n) {
     BuildState *st = D[i].st;

@@ -87,6 +87,7 @@ struct BatchBuildDesc {
 // the kernel variant (mode bound, near-edge counting) and occupancy; each group
 // has its own work counter.
 constexpr int kMaxBuildGroups = 32;
+constexpr int kMaxBuildLaunches = 256;  // work counters of one batched build (groups, or their chunks)
 
 // Work item of the persistent batched build: problem, layer, tile.
 struct BatchItem {

@@ -77,7 +77,7 @@ _lib = None
 
 class MdpServerConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("sweeps_per_step", C.c_int32), ("max_sweeps", C.c_int32),
-                ("pad", C.c_int32), ("tol", C.c_double)]
+                ("build_share", C.c_int32), ("tol", C.c_double)]
 
 
 class MdpServed(C.Structure):
@@ -453,11 +453,11 @@ class Server:
     tensors owned here until its completion is polled."""
 
     def __init__(self, planner: "Planner", pool_bytes: int, max_inflight: int = 64, sweeps_per_step: int = 8,
-                 tol: float = 1e-6, max_sweeps: int = 100000, stream=None):
+                 tol: float = 1e-6, max_sweeps: int = 100000, stream=None, build_share: int = 100):
         self.pl = planner
         self.h = None
         self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=planner.device)
-        cfg = MdpServerConfig(max_inflight, sweeps_per_step, max_sweeps, 0, tol)
+        cfg = MdpServerConfig(max_inflight, sweeps_per_step, max_sweeps, build_share, tol)
         h = C.c_void_p()
         _check(planner.ctx, load().mdp_server_create(planner.ctx, C.byref(cfg), self.pool.data_ptr(),
                                                       self.pool.numel(), C.byref(h)), "mdp_server_create")
