@@ -162,7 +162,8 @@ mdp_status mdp_subgrid_auto(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *e
                             int32_t *hx, int32_t *hy, void *stream);
 
 /* Build the sparse model (Alg. 1 with Alg. 2's per-sample work).
- *   scratch      device buffer of at least mdp_sizes.scratch_bytes
+ *   scratch      device buffer of at least mdp_sizes.scratch_bytes (enough for
+ *                any launch shape the context may have tuned)
  *   stats        host memory written when the stream reaches the end of the
  *                call (pinned memory keeps the call asynchronous)
  * Landing cells are decided in fp32 with one fused multiply-add per mode term
@@ -285,6 +286,34 @@ mdp_status mdp_server_step(mdp_server *srv, void *stream, int32_t *n_active);
 mdp_status mdp_server_poll(mdp_server *srv, mdp_served *out, int32_t max_out, int32_t *n_out);
 mdp_status mdp_server_info(mdp_server *srv, mdp_server_state *out);
 mdp_status mdp_server_destroy(mdp_server *srv);
+
+/* ------------------------------------------------------------------ tuning
+ * The build kernel's launch shape (lanes owning a (cell, action) row: 256, 128
+ * or 64, which fixes the cell tile; realizations per chunk: 64, 128 or 256;
+ * 16- or 32-bit LDS counters) changes only speed: every shape gives the same
+ * model bit for bit. A context keeps one shape per shape class of problem
+ * (actions, sub-grid, mode bound, near-edge counting, log2 of realizations and
+ * cells); mdp_build, batches and servers created on the context use it, others
+ * use the default shape.
+ * mdp_autotune times every shape that fits p on a sample of p's first layers
+ * (about 2e9 landings; the caller's env is read, scratch holds the sample's
+ * model and build scratch, size from mdp_autotune_query), waits for the device,
+ * records the fastest for p's class and reports all timings.
+ * mdp_ctx_set_plan sets a class's shape directly (row_lanes = 0: default). */
+#define MDP_MAX_TUNE 18
+typedef struct mdp_tune_report {
+  int32_t n_candidates;      /* shapes timed                                  */
+  int32_t best;              /* index of the fastest                          */
+  int32_t sample_layers;     /* layers of the timed sample                    */
+  int32_t pad;
+  int32_t row_lanes[MDP_MAX_TUNE], rch[MDP_MAX_TUNE], pack16[MDP_MAX_TUNE];
+  double ms[MDP_MAX_TUNE];   /* best of two timed builds of the sample        */
+} mdp_tune_report;
+mdp_status mdp_autotune_query(const mdp_problem *p, size_t *scratch_bytes);
+mdp_status mdp_autotune(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, void *scratch,
+                        size_t scratch_bytes, mdp_tune_report *out, void *stream);
+mdp_status mdp_ctx_set_plan(mdp_ctx *ctx, const mdp_problem *p, int32_t row_lanes, int32_t rch,
+                            int32_t pack16);
 
 /* Per-kernel timing. While enabled, HIP events are recorded on the caller's
  * stream around every launch of the kernels below; mdp_ctx_profile_read waits

@@ -19,9 +19,28 @@
 
 using namespace mdpk;
 
+// Launch shape of the build kernel: lanes that own a (cell, action) row (the
+// rest of the workgroup helps in the realization phase), realizations per
+// chunk, 16- or 32-bit LDS counters.
+struct PlanChoice {
+  int row_lanes = 0, rch = 0, pack16 = 1;
+};
+
+// Shape class of a problem for the tuned-plan table: everything the candidate
+// set and the kernel's work balance depend on.
+struct TuneKey {
+  int na, W, H, kmax, near, nr_log2, nc_log2;
+  bool operator==(const TuneKey &o) const
+  {
+    return na == o.na && W == o.W && H == o.H && kmax == o.kmax && near == o.near && nr_log2 == o.nr_log2 &&
+           nc_log2 == o.nc_log2;
+  }
+};
+
 struct mdp_ctx {
   int device;
   unsigned int *d_small;  // 256 bytes of device memory for synchronous helpers
+  std::vector<std::pair<TuneKey, PlanChoice>> tuned;  // per shape class, from mdp_autotune / mdp_ctx_set_plan
   char err[512];
   // per-kernel timing (only while profiling is enabled)
   bool profiling = false;
@@ -82,7 +101,53 @@ const char *check_problem(const mdp_problem *p)
   return nullptr;
 }
 
-const char *make_plan(const mdp_problem *p, Plan &pl)
+// LDS bytes of the build kernel for a launch shape.
+size_t plan_lds(int nsg, int na, int row_lanes, int rch, bool pack16)
+{
+  const size_t fixed_lds = 2 * kMaxA * sizeof(float) + 16 * sizeof(uint32_t);
+  const int hw = pack16 ? row_lanes / 2 : row_lanes;
+  const int cells = std::min(row_lanes / na, 32);
+  return (size_t)nsg * hw * 4 + (size_t)cells * (2 * rch + 4) * 4 + fixed_lds;
+}
+
+// Every launch shape the build kernel supports for p (LDS permitting).
+std::vector<PlanChoice> plan_candidates(const mdp_problem *p)
+{
+  std::vector<PlanChoice> out;
+  const int na = p->n_head * p->n_speed;
+  const int nsg = (2 * p->sub_hx + 1) * (2 * p->sub_hy + 1);
+  for (int rl = kBlock; rl >= 64; rl /= 2) {
+    if (rl < na) break;
+    for (int rch = 64; rch <= 256; rch *= 2)
+      for (int pk = 1; pk >= 0; --pk)
+        if (plan_lds(nsg, na, rl, rch, pk != 0) <= kLdsLimit) {
+          PlanChoice c;
+          c.row_lanes = rl;
+          c.rch = rch;
+          c.pack16 = pk;
+          out.push_back(c);
+        }
+  }
+  return out;
+}
+
+// Most cell tiles per layer over the candidate shapes (bounds work-list sizes).
+int max_tiles_per_layer(const mdp_problem *p)
+{
+  const int na = std::max(1, p->n_head * p->n_speed);
+  const int nc = p->nx * p->ny;
+  int cells = 32;
+  for (int rl = 64; rl <= kBlock; rl *= 2)
+    if (rl >= na) {
+      cells = std::min(rl / na, 32);
+      break;
+    }
+  return (nc + std::max(cells, 1) - 1) / std::max(cells, 1);
+}
+
+// choice: a launch shape to use (it must fit), or nullptr for the default
+// (the widest row mapping that fits, 16-bit counters, chunk from the tile).
+const char *make_plan(const mdp_problem *p, Plan &pl, const PlanChoice *choice = nullptr)
 {
   if (const char *e = check_problem(p)) return e;
   pl.na = p->n_head * p->n_speed;
@@ -90,19 +155,33 @@ const char *make_plan(const mdp_problem *p, Plan &pl)
   pl.W = 2 * p->sub_hx + 1;
   pl.nsg = pl.W * (2 * p->sub_hy + 1);
   pl.rows = (int64_t)p->nt * pl.nc * pl.na;
-  pl.pack16 = true;  // n_real <= 65535, so two 16-bit counters fit a word
   pl.kmax = p->n_modes <= 4 ? 4 : (p->n_modes <= 8 ? 8 : (p->n_modes <= 12 ? 12 : 16));
-  const size_t fixed_lds = 2 * kMaxA * sizeof(float) + 16 * sizeof(uint32_t);
   bool ok = false;
+  if (choice) {
+    const int rl = choice->row_lanes;
+    if ((rl == 64 || rl == 128 || rl == 256) && rl >= pl.na && (choice->rch == 64 || choice->rch == 128 ||
+                                                                 choice->rch == 256)) {
+      pl.pack16 = choice->pack16 != 0;
+      pl.lds = plan_lds(pl.nsg, pl.na, rl, choice->rch, pl.pack16);
+      if (pl.lds <= kLdsLimit) {
+        pl.row_lanes = rl;
+        pl.hw = pl.pack16 ? rl / 2 : rl;
+        pl.cells_per_tile = std::min(rl / pl.na, 32);
+        pl.rch = choice->rch;
+        ok = true;
+      }
+    }
+    if (!ok) return "launch shape does not fit this problem";
+  }
+  pl.pack16 = choice ? choice->pack16 != 0 : true;  // n_real <= 65535: two 16-bit counters fit a word
   for (int rl = kBlock; rl >= 64 && !ok; rl /= 2) {
     if (rl < pl.na) break;
-    const int hw = pl.pack16 ? rl / 2 : rl;
     const int cells = std::min(rl / pl.na, 32);
     const int rch = cells <= 8 ? 256 : (cells <= 16 ? 128 : 64);
-    const size_t lds = (size_t)pl.nsg * hw * 4 + (size_t)cells * (2 * rch + 4) * 4 + fixed_lds;
+    const size_t lds = plan_lds(pl.nsg, pl.na, rl, rch, true);
     if (lds <= kLdsLimit) {
       pl.row_lanes = rl;
-      pl.hw = hw;
+      pl.hw = rl / 2;
       pl.cells_per_tile = cells;
       pl.rch = rch;
       pl.lds = lds;
@@ -139,6 +218,42 @@ const char *make_plan(const mdp_problem *p, Plan &pl)
   pl.vi_bytes = align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)) + align_up((size_t)ns * 8) +
                 align_up(sizeof(double) * kViGridMaxHost);
   return nullptr;
+}
+
+TuneKey tune_key(const mdp_problem *p)
+{
+  auto lg = [](int64_t x) {
+    int k = 0;
+    while ((int64_t)1 << k < x) ++k;
+    return k;
+  };
+  TuneKey k;
+  k.na = p->n_head * p->n_speed;
+  k.W = 2 * p->sub_hx + 1;
+  k.H = 2 * p->sub_hy + 1;
+  k.kmax = p->n_modes <= 4 ? 4 : (p->n_modes <= 8 ? 8 : (p->n_modes <= 12 ? 12 : 16));
+  k.near = (p->flags & MDP_FLAG_NEAR_EDGE) ? 1 : 0;
+  k.nr_log2 = lg(p->n_real);
+  k.nc_log2 = lg((int64_t)p->nx * p->ny);
+  return k;
+}
+
+// The tuned launch shape of p's class on this context, or nullptr.
+const PlanChoice *tuned_choice(const mdp_ctx *ctx, const mdp_problem *p)
+{
+  if (!ctx || !p) return nullptr;
+  const TuneKey k = tune_key(p);
+  for (const auto &e : ctx->tuned)
+    if (e.first == k) return &e.second;
+  return nullptr;
+}
+
+// Plan of p on ctx: its tuned shape when it fits, else the default.
+const char *ctx_plan(const mdp_ctx *ctx, const mdp_problem *p, Plan &pl)
+{
+  if (const PlanChoice *c = tuned_choice(ctx, p))
+    if (!make_plan(p, pl, c)) return nullptr;
+  return make_plan(p, pl);
 }
 
 bool is_device_ptr(const void *ptr)
@@ -369,7 +484,12 @@ mdp_status mdp_build_query(const mdp_problem *p, mdp_sizes *out)
   out->n_sg = pl.nsg;
   out->nnz_upper = pl.rows * (int64_t)std::min(pl.nsg, p->n_real);
   out->n_missions = popcount3(p->mission_mask);
-  out->scratch_bytes = (int64_t)std::max(pl.build_bytes, pl.vi_bytes);
+  size_t build_bytes = pl.build_bytes;  // enough for any launch shape a context may use
+  for (const PlanChoice &c : plan_candidates(p)) {
+    Plan q;
+    if (!make_plan(p, q, &c)) build_bytes = std::max(build_bytes, q.build_bytes);
+  }
+  out->scratch_bytes = (int64_t)std::max(build_bytes, pl.vi_bytes);
   const int64_t tm = p->mean_time_varying ? p->nt : 1, tp = p->mode_time_varying ? p->nt : 1;
   out->env_bytes = 4 * (2 * tm * pl.nc + 2 * tp * (int64_t)p->n_modes * pl.nc +
                         (int64_t)p->nt * p->n_modes * p->n_real) +
@@ -430,15 +550,26 @@ mdp_status mdp_subgrid_auto(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *e
   return MDP_OK;
 }
 
+static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
+                                  void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream,
+                                  const Plan &pl);
+
 mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
                      void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream)
 {
   if (!ctx) return MDP_E_INVALID;
   Plan pl;
-  if (const char *e = make_plan(p, pl)) {
+  if (const char *e = ctx_plan(ctx, p, pl)) {
     set_err(ctx, "%s", e);
     return MDP_E_INVALID;
   }
+  return build_with_plan(ctx, p, env, model, scratch, scratch_bytes, stats, stream, pl);
+}
+
+static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
+                                  void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream,
+                                  const Plan &pl)
+{
   if (const char *e = check_env(p, env)) {
     set_err(ctx, "%s", e);
     return MDP_E_INVALID;
@@ -542,6 +673,156 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
   V.inv_nr = 1.0 / (double)p->n_real;
 }
 
+// ---------------------------------------------------------------- autotuning
+// The sample a launch shape is timed on: the problem's first layers, enough
+// of them for about kTuneSamples landings.
+static constexpr double kTuneSamples = 2e9;
+
+static const char *tune_sample(const mdp_problem *p, mdp_problem &q)
+{
+  if (const char *e = check_problem(p)) return e;
+  q = *p;
+  const double per_layer = (double)p->nx * p->ny * p->n_head * p->n_speed * p->n_real;
+  q.nt = (int32_t)std::max(1.0, std::min((double)p->nt, std::ceil(kTuneSamples / std::max(per_layer, 1.0))));
+  return nullptr;
+}
+
+struct TuneLayout {
+  size_t row_ptr, col, cnt, reward, scratch, total, build_bytes;
+  int64_t rows, cap;
+};
+
+static const char *tune_layout(const mdp_problem *q, TuneLayout &T)
+{
+  Plan pl;
+  if (const char *e = make_plan(q, pl)) return e;
+  T.rows = pl.rows;
+  T.cap = pl.rows * (int64_t)std::min(pl.nsg, q->n_real);
+  T.build_bytes = pl.build_bytes;
+  for (const PlanChoice &c : plan_candidates(q)) {
+    Plan x;
+    if (!make_plan(q, x, &c)) T.build_bytes = std::max(T.build_bytes, x.build_bytes);
+  }
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off = align_up(off + b);
+    return at;
+  };
+  T.row_ptr = take(8 * (size_t)(T.rows + 1));
+  T.col = take(4 * (size_t)T.cap);
+  T.cnt = take(2 * (size_t)T.cap);
+  T.reward = take(4 * (size_t)T.rows * popcount3(q->mission_mask));
+  T.scratch = take(T.build_bytes);
+  T.total = off;
+  return nullptr;
+}
+
+mdp_status mdp_autotune_query(const mdp_problem *p, size_t *scratch_bytes)
+{
+  if (!scratch_bytes) return MDP_E_INVALID;
+  mdp_problem q;
+  TuneLayout T;
+  if (tune_sample(p, q) || tune_layout(&q, T)) return MDP_E_INVALID;
+  *scratch_bytes = T.total;
+  return MDP_OK;
+}
+
+mdp_status mdp_autotune(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, void *scratch, size_t scratch_bytes,
+                        mdp_tune_report *out, void *stream)
+{
+  if (!ctx || !out) return MDP_E_INVALID;
+  mdp_problem q;
+  TuneLayout T;
+  if (const char *e = tune_sample(p, q)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  if (const char *e = tune_layout(&q, T)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  if (!is_device_ptr(scratch) || scratch_bytes < T.total) {
+    set_err(ctx, "autotune scratch needs %zu device bytes", T.total);
+    return MDP_E_SCRATCH;
+  }
+  const std::vector<PlanChoice> cands = plan_candidates(&q);
+  if (cands.empty() || (int)cands.size() > MDP_MAX_TUNE) {
+    set_err(ctx, "no launch shape fits this problem");
+    return MDP_E_INVALID;
+  }
+  char *sc = (char *)scratch;
+  mdp_model M{(int64_t *)(sc + T.row_ptr), (int32_t *)(sc + T.col), (uint16_t *)(sc + T.cnt),
+              (float *)(sc + T.reward), T.cap};
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(ctx, e, "autotune events");
+  }
+  memset(out, 0, sizeof(*out));
+  out->sample_layers = q.nt;
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  mdp_status rc = MDP_OK;
+  int best = -1;
+  for (size_t i = 0; i < cands.size() && rc == MDP_OK; ++i) {
+    Plan pl;
+    make_plan(&q, pl, &cands[i]);
+    mdp_build_stats st;
+    double ms_best = 1e30;
+    for (int rep = 0; rep < 3 && rc == MDP_OK; ++rep) {  // first run warms up
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(ctx, e, "autotune record");
+      if (rc == MDP_OK) rc = build_with_plan(ctx, &q, env, &M, sc + T.scratch, T.build_bytes, &st, stream, pl);
+      if (rc == MDP_OK && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(ctx, e, "autotune record");
+      if (rc == MDP_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(ctx, e, "autotune sync");
+      float ms = 0.0f;
+      if (rc == MDP_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = hip_fail(ctx, e, "elapsed");
+      if (rc == MDP_OK && st.status != MDP_OK) {
+        set_err(ctx, "autotune sample build failed: %s", mdp_status_str(st.status));
+        rc = st.status;
+      }
+      if (rc == MDP_OK && rep > 0) ms_best = std::min(ms_best, (double)ms);
+    }
+    out->row_lanes[i] = cands[i].row_lanes;
+    out->rch[i] = cands[i].rch;
+    out->pack16[i] = cands[i].pack16;
+    out->ms[i] = ms_best;
+    if (rc == MDP_OK && (best < 0 || ms_best < out->ms[best])) best = (int)i;
+  }
+  ctx->profiling = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != MDP_OK) return rc;
+  out->n_candidates = (int32_t)cands.size();
+  out->best = best;
+  return mdp_ctx_set_plan(ctx, p, cands[best].row_lanes, cands[best].rch, cands[best].pack16);
+}
+
+mdp_status mdp_ctx_set_plan(mdp_ctx *ctx, const mdp_problem *p, int32_t row_lanes, int32_t rch, int32_t pack16)
+{
+  if (!ctx || !p) return MDP_E_INVALID;
+  const TuneKey k = tune_key(p);
+  for (size_t i = 0; i < ctx->tuned.size(); ++i)
+    if (ctx->tuned[i].first == k) {
+      ctx->tuned.erase(ctx->tuned.begin() + (long)i);
+      break;
+    }
+  if (row_lanes == 0) return MDP_OK;  // back to the default shape
+  PlanChoice c;
+  c.row_lanes = row_lanes;
+  c.rch = rch;
+  c.pack16 = pack16 ? 1 : 0;
+  Plan pl;
+  if (const char *e = make_plan(p, pl, &c)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  ctx->tuned.push_back({k, c});
+  return MDP_OK;
+}
+
 static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
                            Plan &pl, VIParams &V)
 {
@@ -635,13 +916,13 @@ struct BatchLayout {
 };
 
 const char *batch_layout(int n, const mdp_problem *probs, int64_t pool_entries, std::vector<Plan> &plans,
-                         BatchLayout &L, int64_t &pool_cap)
+                         BatchLayout &L, int64_t &pool_cap, const mdp_ctx *ctx = nullptr)
 {
   if (n < 1 || n > kMaxBatch) return "batch size must be in [1, 1024]";
   plans.resize(n);
   int64_t rows_all = 0;
   for (int i = 0; i < n; ++i) {
-    if (const char *e = make_plan(&probs[i], plans[i])) return e;
+    if (const char *e = ctx_plan(ctx, &probs[i], plans[i])) return e;
     rows_all += plans[i].rows;
   }
   pool_cap = pool_entries > 0 ? pool_entries : 4 * rows_all + 1024;
@@ -665,7 +946,7 @@ const char *batch_layout(int n, const mdp_problem *probs, int64_t pool_entries, 
   L.v_alt.resize(n);
   for (int i = 0; i < n; ++i) {
     const Plan &pl = plans[i];
-    const size_t items = (size_t)probs[i].nt * pl.tiles_per_layer;
+    const size_t items = (size_t)probs[i].nt * max_tiles_per_layer(&probs[i]);  // any launch shape
     L.row_nnz[i] = take(4 * (size_t)pl.rows);
     L.row_off[i] = take(4 * (size_t)pl.rows);
     L.item_total[i] = take(4 * items);
@@ -920,7 +1201,7 @@ mdp_status mdp_batch_create(mdp_ctx *ctx, int32_t n, const mdp_problem *probs, c
   std::vector<Plan> plans;
   BatchLayout L;
   int64_t pool_cap = 0;
-  if (const char *e = batch_layout(n, probs, pool_entries, plans, L, pool_cap)) {
+  if (const char *e = batch_layout(n, probs, pool_entries, plans, L, pool_cap, ctx)) {
     set_err(ctx, "%s", e);
     return MDP_E_INVALID;
   }
@@ -1211,7 +1492,7 @@ ReqSizes req_sizes(const mdp_problem *p, const Plan &pl)
            align_up(4 * (size_t)z.ns) + align_up(sizeof(VIState));
   z.col = align_up(4 * (size_t)z.cap);
   z.cnt = align_up(2 * (size_t)z.cap);
-  const size_t items = (size_t)p->nt * pl.tiles_per_layer;
+  const size_t items = (size_t)p->nt * max_tiles_per_layer(p);
   z.build = align_up(sizeof(BuildState)) + align_up(sizeof(mdp_build_stats)) + 2 * align_up(4 * (size_t)z.rows) +
             align_up(4 * items) + 2 * align_up(8 * items) + align_up(8 * (size_t)z.cap);
   return z;
@@ -1684,7 +1965,7 @@ mdp_status mdp_server_submit(mdp_server *S, const mdp_problem *p, const mdp_env 
   r->mission = mission;
   r->h_pi = h_pi;
   r->h_v = h_v;
-  if (const char *m = make_plan(&r->p, r->pl)) {
+  if (const char *m = ctx_plan(S->ctx, &r->p, r->pl)) {
     set_err(S->ctx, "request %lld: %s", (long long)tag, m);
     delete r;
     return MDP_E_INVALID;

@@ -75,6 +75,15 @@ class MdpViStats(C.Structure):
 _lib = None
 
 
+MDP_MAX_TUNE = 18
+
+
+class MdpTuneReport(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("best", C.c_int32), ("sample_layers", C.c_int32),
+                ("pad", C.c_int32), ("row_lanes", C.c_int32 * MDP_MAX_TUNE), ("rch", C.c_int32 * MDP_MAX_TUNE),
+                ("pack16", C.c_int32 * MDP_MAX_TUNE), ("ms", C.c_double * MDP_MAX_TUNE)]
+
+
 class MdpServerConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("sweeps_per_step", C.c_int32), ("max_sweeps", C.c_int32),
                 ("build_share", C.c_int32), ("tol", C.c_double)]
@@ -120,6 +129,9 @@ def load():
             "mdp_batch_capture": ([vp, C.c_double, C.c_int32, vp], C.c_int32),
             "mdp_batch_replay": ([vp, vp], C.c_int32),
             "mdp_batch_destroy": ([vp], C.c_int32),
+            "mdp_autotune_query": ([P, C.POINTER(C.c_size_t)], C.c_int32),
+            "mdp_autotune": ([vp, P, C.POINTER(MdpEnv), vp, C.c_size_t, C.POINTER(MdpTuneReport), vp], C.c_int32),
+            "mdp_ctx_set_plan": ([vp, P, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
             "mdp_server_footprint": ([P, C.POINTER(C.c_size_t)], C.c_int32),
             "mdp_server_create": ([vp, C.POINTER(MdpServerConfig), vp, C.c_size_t, C.POINTER(vp)], C.c_int32),
             "mdp_server_submit": ([vp, P, C.POINTER(MdpEnv), C.c_int32, vp, vp, C.c_int64], C.c_int32),
@@ -143,7 +155,8 @@ EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_err
             "mdp_ctx_profile_read", "mdp_batch_query", "mdp_batch_create", "mdp_batch_build", "mdp_batch_solve",
             "mdp_batch_stats", "mdp_batch_capture", "mdp_batch_replay", "mdp_batch_destroy",
             "mdp_server_footprint", "mdp_server_create", "mdp_server_submit", "mdp_server_step",
-            "mdp_server_poll", "mdp_server_info", "mdp_server_destroy"]
+            "mdp_server_poll", "mdp_server_info", "mdp_server_destroy", "mdp_autotune_query", "mdp_autotune",
+            "mdp_ctx_set_plan"]
 MDP_KERNEL_BUILD, MDP_KERNEL_VI_SWEEP, MDP_KERNEL_POLICY, MDP_KERNEL_COPY = 0, 1, 2, 3
 
 
@@ -512,3 +525,28 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def mdp_autotune(ctx, problem: dict, env: dict, stream=None) -> dict:
+    """Time every build launch shape on a sample of the problem's first layers and keep
+    the fastest on the context for the problem's shape class (waits for the device)."""
+    ps = problem_struct(problem)
+    n = C.c_size_t()
+    rc = load().mdp_autotune_query(C.byref(ps), C.byref(n))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_autotune_query")
+    scratch = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+    es = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
+    rep = MdpTuneReport()
+    rc = load().mdp_autotune(ctx, C.byref(ps), C.byref(es), scratch.data_ptr(), scratch.numel(), C.byref(rep),
+                             _stream_handle(stream))
+    _check(ctx, rc, "mdp_autotune")
+    k = rep.n_candidates
+    shapes = [dict(row_lanes=rep.row_lanes[i], rch=rep.rch[i], pack16=rep.pack16[i], ms=rep.ms[i]) for i in range(k)]
+    return dict(best=rep.best, sample_layers=rep.sample_layers, shapes=shapes)
+
+
+def mdp_ctx_set_plan(ctx, problem: dict, row_lanes: int, rch: int, pack16: int) -> None:
+    """Use this build launch shape for the problem's shape class (row_lanes = 0: default)."""
+    rc = load().mdp_ctx_set_plan(ctx, C.byref(problem_struct(problem)), row_lanes, rch, pack16)
+    _check(ctx, rc, "mdp_ctx_set_plan")

@@ -78,3 +78,18 @@ def test_query_rejects_oversized_subgrid(lib):
     w = W.config1(nt=2, n_real=10, sub_h=40)
     with pytest.raises(mdp.MdpError):
         mdp.mdp_build_query(w.problem)
+
+
+def test_autotune_query_sizes(lib):
+    """The tuning sample's scratch is sized on the host; invalid problems are refused."""
+    import ctypes as C
+
+    from paper_2109_00857_amd import mdp, workloads as W
+
+    w = W.config2()
+    n = C.c_size_t()
+    assert lib.mdp_autotune_query(C.byref(mdp.problem_struct(w.problem)), C.byref(n)) == mdp.MDP_OK
+    sz = mdp.mdp_build_query(w.problem)
+    assert 0 < n.value < sz["n_rows"] * 40 + sz["scratch_bytes"]
+    bad = dict(w.problem, nx=0)
+    assert lib.mdp_autotune_query(C.byref(mdp.problem_struct(bad)), C.byref(n)) == mdp.MDP_E_INVALID
