@@ -307,6 +307,7 @@ def main():
     ap.add_argument("--build-share", type=int, default=50,
                     help="percent of the GPU's resident workgroups a served build batch may hold")
     ap.add_argument("--serve-sweeps", type=int, default=32, help="most sweeps per served scheduler step")
+    ap.add_argument("--no-autotune", action="store_true", help="build with the default launch shape")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -336,6 +337,9 @@ def main():
     missions = w.missions()
     pl = mdp.Planner(0)
     env = pl.upload_env(w)
+    tune = None
+    if not args.no_autotune:  # untimed: pick the build launch shape for this shape class
+        tune = mdp.mdp_autotune(pl.ctx, p, env)
     sizes = mdp.mdp_build_query(p)
     model, st0 = pl.build(p, env)  # sizes the model (untimed)
     assert st0["status"] == mdp.MDP_OK, st0
@@ -445,6 +449,8 @@ def main():
         "vi_ms_per_step": ms_v / args.steps,
         "policy_ms_per_step": kt[mdp.MDP_KERNEL_POLICY][1] / args.steps,
         "copy_ms_per_step": kt[mdp.MDP_KERNEL_COPY][1] / args.steps,
+        "build_shape": (None if tune is None else dict(tune["shapes"][tune["best"]], sample_layers=tune["sample_layers"],
+                                                        default_ms=tune["shapes"][tune["default"]]["ms"])),
         "roofline": dominant,
         "rooflines": {"build": roof_build, "vi_sweep": roof_vi},
     }

@@ -296,8 +296,9 @@ mdp_status mdp_server_destroy(mdp_server *srv);
  * cells); mdp_build, batches and servers created on the context use it, others
  * use the default shape.
  * mdp_autotune times every shape that fits p on a sample of p's first layers
- * (about 2e9 landings; the caller's env is read, scratch holds the sample's
- * model and build scratch, size from mdp_autotune_query), waits for the device,
+ * (16384 cell tiles of the default shape, or all layers; the caller's env is
+ * read, scratch holds the sample's model and build scratch, size from
+ * mdp_autotune_query), waits for the device,
  * records the fastest for p's class and reports all timings.
  * mdp_ctx_set_plan sets a class's shape directly (row_lanes = 0: default). */
 #define MDP_MAX_TUNE 18
@@ -305,7 +306,7 @@ typedef struct mdp_tune_report {
   int32_t n_candidates;      /* shapes timed                                  */
   int32_t best;              /* index of the fastest                          */
   int32_t sample_layers;     /* layers of the timed sample                    */
-  int32_t pad;
+  int32_t default_shape;     /* index of the shape used without tuning        */
   int32_t row_lanes[MDP_MAX_TUNE], rch[MDP_MAX_TUNE], pack16[MDP_MAX_TUNE];
   double ms[MDP_MAX_TUNE];   /* best of two timed builds of the sample        */
 } mdp_tune_report;

@@ -675,15 +675,16 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
 
 // ---------------------------------------------------------------- autotuning
 // The sample a launch shape is timed on: the problem's first layers, enough
-// of them for about kTuneSamples landings.
-static constexpr double kTuneSamples = 2e9;
+// of them for kTuneTiles cell tiles of the default shape (many waves of
+// resident workgroups, so the timing is the steady state, not the tail).
+static constexpr double kTuneTiles = 16384;
 
 static const char *tune_sample(const mdp_problem *p, mdp_problem &q)
 {
-  if (const char *e = check_problem(p)) return e;
+  Plan pl;
+  if (const char *e = make_plan(p, pl)) return e;
   q = *p;
-  const double per_layer = (double)p->nx * p->ny * p->n_head * p->n_speed * p->n_real;
-  q.nt = (int32_t)std::max(1.0, std::min((double)p->nt, std::ceil(kTuneSamples / std::max(per_layer, 1.0))));
+  q.nt = (int32_t)std::max(1.0, std::min((double)p->nt, std::ceil(kTuneTiles / std::max(pl.tiles_per_layer, 1))));
   return nullptr;
 }
 
@@ -797,6 +798,12 @@ mdp_status mdp_autotune(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, 
   if (rc != MDP_OK) return rc;
   out->n_candidates = (int32_t)cands.size();
   out->best = best;
+  out->default_shape = -1;
+  Plan dpl;
+  if (!make_plan(&q, dpl))
+    for (size_t i = 0; i < cands.size(); ++i)
+      if (cands[i].row_lanes == dpl.row_lanes && cands[i].rch == dpl.rch && (cands[i].pack16 != 0) == dpl.pack16)
+        out->default_shape = (int32_t)i;
   return mdp_ctx_set_plan(ctx, p, cands[best].row_lanes, cands[best].rch, cands[best].pack16);
 }
 

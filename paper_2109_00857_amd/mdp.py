@@ -80,7 +80,7 @@ MDP_MAX_TUNE = 18
 
 class MdpTuneReport(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("best", C.c_int32), ("sample_layers", C.c_int32),
-                ("pad", C.c_int32), ("row_lanes", C.c_int32 * MDP_MAX_TUNE), ("rch", C.c_int32 * MDP_MAX_TUNE),
+                ("default_shape", C.c_int32), ("row_lanes", C.c_int32 * MDP_MAX_TUNE), ("rch", C.c_int32 * MDP_MAX_TUNE),
                 ("pack16", C.c_int32 * MDP_MAX_TUNE), ("ms", C.c_double * MDP_MAX_TUNE)]
 
 
@@ -543,7 +543,7 @@ def mdp_autotune(ctx, problem: dict, env: dict, stream=None) -> dict:
     _check(ctx, rc, "mdp_autotune")
     k = rep.n_candidates
     shapes = [dict(row_lanes=rep.row_lanes[i], rch=rep.rch[i], pack16=rep.pack16[i], ms=rep.ms[i]) for i in range(k)]
-    return dict(best=rep.best, sample_layers=rep.sample_layers, shapes=shapes)
+    return dict(best=rep.best, default=rep.default_shape, sample_layers=rep.sample_layers, shapes=shapes)
 
 
 def mdp_ctx_set_plan(ctx, problem: dict, row_lanes: int, rch: int, pack16: int) -> None:
