@@ -191,16 +191,22 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep(const VIParams P, const dou
   if (threadIdx.x == 0) wg_res[blockIdx.x] = m;
 }
 
+constexpr int kCloseBlock = 1024;  // threads of the sweep-closing kernel (8 partial maxima each at most)
+
 // Close one sweep: count, last residual, done flag.
-__global__ __launch_bounds__(kBlock) void k_vi_close(const VIParams P, const double *wg_res, int grid)
+__global__ __launch_bounds__(kCloseBlock) void k_vi_close(const VIParams P, const double *wg_res, int grid)
 {
-  __shared__ double wmax[kBlock / 64];
+  __shared__ double wmax[kCloseBlock / 64];
   VIState *st = P.st;
   if (st->done) return;
   double m = 0.0;
-  for (int w = threadIdx.x; w < grid; w += kBlock) m = fmax(m, wg_res[w]);
-  m = block_max(m, wmax);
+  for (int w = threadIdx.x; w < grid; w += kCloseBlock) m = fmax(m, wg_res[w]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int w = 1; w < kCloseBlock / 64; ++w) m = fmax(m, wmax[w]);
     st->sweeps += 1;
     st->last_res = m;
     if (m < P.tol) st->done = 1;
@@ -311,17 +317,21 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep_batched(const BatchVIDesc *
 }
 
 // Close the sweep of each problem (one block per problem).
-__global__ __launch_bounds__(kBlock) void k_vi_close_batched(const BatchVIDesc *D, int n, int grid,
-                                                              const double *wg_res, double tol)
+__global__ __launch_bounds__(kCloseBlock) void k_vi_close_batched(const BatchVIDesc *D, int n, int grid,
+                                                                   const double *wg_res, double tol)
 {
-  __shared__ double wmax[kBlock / 64];
+  __shared__ double wmax[kCloseBlock / 64];
   const int i = blockIdx.x;
   VIState *st = D[i].st;
   if (st->done) return;
   double m = 0.0;
-  for (int w = threadIdx.x; w < grid; w += kBlock) m = fmax(m, wg_res[(int64_t)w * n + i]);
-  m = block_max(m, wmax);
+  for (int w = threadIdx.x; w < grid; w += kCloseBlock) m = fmax(m, wg_res[(int64_t)w * n + i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int w = 1; w < kCloseBlock / 64; ++w) m = fmax(m, wmax[w]);
     st->sweeps += 1;
     st->last_res = m;
     if (m < tol) st->done = 1;
@@ -430,7 +440,7 @@ hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, i
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nb, std::min(P.n_wg, kViGridMax)));
   hipLaunchKernelGGL(k_vi_sweep, dim3(grid), dim3(kBlock), single_lds(P), s, P, vin, vout, t_hi, wg_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_vi_close, dim3(1), dim3(kBlock), 0, s, P, (const double *)wg_res, grid);
+  hipLaunchKernelGGL(k_vi_close, dim3(1), dim3(kCloseBlock), 0, s, P, (const double *)wg_res, grid);
   return hipGetLastError();
 }
 
@@ -467,7 +477,7 @@ hipError_t launch_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *b
 hipError_t launch_vi_close_batched(const BatchVIDesc *D, int n, int grid, const double *wg_res, double tol,
                                    hipStream_t s)
 {
-  hipLaunchKernelGGL(k_vi_close_batched, dim3(n), dim3(kBlock), 0, s, D, n, grid, wg_res, tol);
+  hipLaunchKernelGGL(k_vi_close_batched, dim3(n), dim3(kCloseBlock), 0, s, D, n, grid, wg_res, tol);
   return hipGetLastError();
 }
 
