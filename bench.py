@@ -31,10 +31,10 @@ HBM_BW = 8.0e12                        # bytes/s
 # WRITE_SIZE x1.000 by a plain 1 GiB copy). They hold for the kernel source
 # whose sha256 prefix is given; after any change the traffic is reported null.
 MEASURED_TRAFFIC = {
-    "k_vi_sweep": dict(read=353218147, write=5125125, src="paper_2109_00857_amd/csrc/vi.hip",
-                       sha256="76b2f172ae8c2c3e"),
-    "k_build": dict(read=444089129, write=882361744, src="paper_2109_00857_amd/csrc/build.hip",
-                    sha256="827a8dc5a21ee570"),
+    "k_vi_sweep": dict(read=353251167, write=5125185, src="paper_2109_00857_amd/csrc/vi.hip",
+                       sha256="beb1c305908880f1"),
+    "k_build": dict(read=444020928, write=882346368, src="paper_2109_00857_amd/csrc/build.hip",
+                    sha256="4637964e6ac9181b"),
 }
 
 
@@ -194,7 +194,7 @@ def served_inputs(pl, seconds: float, rate: float):
     return arr, reqs, envs
 
 
-def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_share: int = 50,
+def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_share: int = 100,
                sweeps_per_step: int = 32, sequential: bool = True, trace=None) -> dict:
     """The served trace through the continuous-batching server, then the same trace
     through sequential plain solves (first come, first served, one at a time)."""
@@ -304,7 +304,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-trace leg")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the served trace")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrival rate (per second)")
-    ap.add_argument("--build-share", type=int, default=50,
+    ap.add_argument("--build-share", type=int, default=100,
                     help="percent of the GPU's resident workgroups a served build batch may hold")
     ap.add_argument("--serve-sweeps", type=int, default=32, help="most sweeps per served scheduler step")
     ap.add_argument("--no-autotune", action="store_true", help="build with the default launch shape")

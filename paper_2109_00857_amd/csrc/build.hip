@@ -93,6 +93,14 @@ __device__ inline int mad_i24(int a, int b, int c)
   return r;
 }
 
+// a * b + c with a wave-uniform b taken straight from a scalar register.
+__device__ inline int mad_i24_s(int a, int b, int c)
+{
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
 __device__ inline uint64_t pack_entry(int32_t col, uint32_t cnt)
 {
   return (uint64_t)(uint32_t)col | ((uint64_t)cnt << 32);
@@ -168,6 +176,20 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   const float *mu_t = P.mu + (size_t)t * P.K * P.nr;
 
   uint32_t near_cnt = 0, esc_cnt = 0;
+  // Coefficients of this lane's realization in chunk r0. Coefficients beyond K
+  // are zero, so their fma(0, phi, u) terms return u exactly and the landing
+  // arithmetic is the K-term sum; loads are clamped to mode K-1 and to the last
+  // realization (every load in bounds) instead of branching.
+  auto load_mu = [&](int r0, float *m) {
+    const int r = min(r0 + rlane, P.nr - 1);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const float val = mu_t[(size_t)min(k, P.K - 1) * P.nr + r];
+      m[k] = (k < P.K) ? val : 0.0f;
+    }
+  };
+  float m[KMAX];  // coefficients of the current chunk
+  load_mu(0, m);
   __syncthreads();
 
   for (int r0 = 0; r0 < P.nr; r0 += P.rch) {
@@ -175,16 +197,6 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
     // ---------------- phase A: lane = realization
     {
       const bool rv = rlane < nloc;
-      const int r = rv ? r0 + rlane : r0;  // clamped: every load below is in bounds
-      // Coefficients beyond K are zero, so their fma(0, phi, u) terms return u
-      // exactly and the landing arithmetic is the K-term sum; loads are clamped
-      // to mode K-1 instead of branching per term.
-      float m[KMAX];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        const float val = mu_t[(size_t)min(k, P.K - 1) * P.nr + r];
-        m[k] = (k < P.K) ? val : 0.0f;
-      }
       for (int q = qg; q < ncell; q += nqg) {
         const int cq = c0 + q;
         const int qi = cq % P.nx, qj = cq / P.nx;
@@ -238,7 +250,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
         const float Y = py + hya;
         const int ix = cvt_floor(X);
         const int iy = cvt_floor(Y);
-        lds_add(mad_i24(mad_i24(iy, W, ix), HW4, base4), inc);
+        lds_add(mad_i24_s(mad_i24_s(iy, W, ix), HW4, base4), inc);
         if (NEAR)
           near_cnt += ((fabsf(X - rintf(X)) < P.eps_x) || (fabsf(Y - rintf(Y)) < P.eps_y)) ? 1u : 0u;
       };
@@ -275,6 +287,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
       }
     }
     __syncthreads();
+    if (r0 + P.rch < P.nr) load_mu(r0 + P.rch, m);
   }
 
   // ---------------- diagnostics
