@@ -163,12 +163,15 @@ struct VIParams {
   VIState *st;
 };
 
-// LDS of the sweep / policy kernels, in doubles: Q of the block's rows and
-// the wave maxima; then (batched kernels) per-problem residuals and block
-// starts; then the window of v(t + 1).
+// LDS of the sweep / policy kernels, in doubles: the staged products of one
+// chunk of the block's entries (Q of the block's rows reuses it once every row
+// sum is done), the wave maxima; then (batched kernels) per-problem residuals,
+// block starts and sweep states; then the window of v(t + 1).
 constexpr int kViRows = 2 * kBlock;
-constexpr int kViQ = 0;
-constexpr int kViWmax = kViQ + kViRows;
+constexpr int kViChunk = 2048;                         // entries staged per round (>= kViRows)
+constexpr int kViProd = 0;
+constexpr int kViQ = 0;                                // aliases the products
+constexpr int kViWmax = kViProd + kViChunk;
 constexpr int kViFixed = kViWmax + 8;
 constexpr int kViWinPerThread = 8;                             // window values a thread stages
 constexpr size_t kViWinBudget = (size_t)kViWinPerThread * kBlock * 8;  // bytes of the v window at most

@@ -1,17 +1,19 @@
 // Value iteration and greedy policy on the CSR model (Sec. II-B update rule).
 //
 // A workgroup takes a block of S cells of one decision layer t (their S * N_a
-// rows are contiguous, at most 512; two rows per thread). For the block every
-// thread first issues all loads that do not depend on each other: the row
-// pointers and rewards of its rows, the old value of its state, its share of
-// the window of v_old(t + 1) that the rows can reach (grid rows within the
-// sub-grid half height of the block's rows), and the first entries (col, cnt)
-// of its rows. The window goes to LDS, then each thread adds its rows'
-//     Q(s, a) = R(s, a) + (sum_k cnt_k * v_old[col_k]) / N_r      (fp64)
-// in ascending entry order (the sinks DEAD and TARGET contribute 0), two
-// entries of each row per round, and one thread per state takes max_a Q
-// (first maximum on ties). The per-row sum has a fixed order, so every path
-// (single problem, batch, server) gives the same bits.
+// rows are contiguous, at most 512; two rows per thread). Two rounds of
+// global loads per block:
+//   1. the block's entry range, its rows' entry offsets and rewards, each
+//      state's old value, and the window of v_old(t + 1) that the rows can
+//      reach (grid rows within the sub-grid half height of the block's rows);
+//   2. the block's entries (col, cnt), coalesced, one lane per entry.
+// The window goes to LDS; each lane forms cnt * v_old[col] for its entries
+// (the sinks DEAD and TARGET contribute 0) and stages the products in LDS;
+// then each row's thread adds its products in ascending entry order (fp64),
+//     Q(s, a) = R(s, a) + (sum_k cnt_k * v_old[col_k]) / N_r,
+// and one thread per state takes max_a Q (first maximum on ties). The per-row
+// sum has a fixed order, so every path (single problem, batch, server) gives
+// the same bits.
 //
 // Every transition goes from layer t to layer t + 1 or to a sink, and layer
 // T - 1 reaches only sinks, so after k sweeps the layers t >= T - k hold
@@ -32,41 +34,6 @@
 namespace mdpk {
 
 constexpr int kViGridMax = 8192;
-constexpr int kViUnroll = 2;  // entries of each row loaded per round
-
-// Loads of the next kViUnroll entries of rows [lo, hi) (a valid index when past the end).
-__device__ inline void vi_load(const VIParams &P, int64_t lo, int64_t hi, uint32_t *c, uint16_t *n)
-{
-#pragma unroll
-  for (int u = 0; u < kViUnroll; ++u) {
-    const int64_t k = lo + u;
-    const bool ok = k < hi;
-    const int64_t kk = ok ? k : 0;
-    const uint32_t cv = (uint32_t)P.col[kk];
-    const uint16_t nv = P.cnt[kk];
-    c[u] = ok ? cv : 0xffffffffu;
-    n[u] = ok ? nv : (uint16_t)0;
-  }
-}
-
-// Add loaded entries to acc in order; the window covers [wbase, wbase + wn).
-__device__ inline void vi_add(const VIParams &P, const double *vin, const double *vwin, int64_t wbase, int wn,
-                              int64_t lo, int64_t hi, const uint32_t *c, const uint16_t *n, double &acc)
-{
-  const uint32_t ns32 = (uint32_t)P.ns;
-#pragma unroll
-  for (int u = 0; u < kViUnroll; ++u) {
-    if (lo + u < hi) {
-      const uint32_t cc = c[u];
-      double vv = 0.0;
-      if (cc < ns32) {
-        const int64_t w = (int64_t)cc - wbase;
-        vv = (w >= 0 && w < wn) ? vwin[w] : vin[cc];
-      }
-      acc += (double)n[u] * vv;
-    }
-  }
-}
 
 // Q of the rows of cells [c0, c0 + S) of layer t, then per state either the
 // new value (returns the block's max |v_new - v_old|) or the first argmax.
@@ -74,14 +41,19 @@ template <bool POLICY>
 __device__ inline double vi_block(const VIParams &P, const double *vin, double *vout, int32_t *pi, int t, int c0,
                                   double *sm, double *vwin)
 {
+  double *prod = sm + kViProd;
   double *q = sm + kViQ;
   const int tid = threadIdx.x;
   const int nst = min(P.states_per_wg, P.nc - c0);
   const int nr = nst * P.na;
   const int64_t s0 = (int64_t)t * P.nc + c0;
   const int64_t row0 = s0 * P.na;
-  // independent loads: row pointers (clamped into col / cnt), rewards, own value
-  int64_t lo[2], hi[2];
+  // ---- round 1. The block's entries [eb, ee), clamped so that a malformed
+  // row pointer can neither read outside col / cnt nor loop long.
+  const int64_t eb = min(max(P.row_ptr[row0], (int64_t)0), P.cap);
+  const int64_t ee = min(min(max(P.row_ptr[row0 + nr], eb), P.cap), eb + (int64_t)nr * P.max_row);
+  const int E = (int)(ee - eb);
+  int lo[2], hi[2];
   float rr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -89,8 +61,8 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     lo[h] = hi[h] = 0;
     rr[h] = 0.0f;
     if (r < nr) {
-      lo[h] = max(P.row_ptr[row0 + r], (int64_t)0);
-      hi[h] = min(min(P.row_ptr[row0 + r + 1], P.cap), lo[h] + P.max_row);
+      lo[h] = (int)(min(max(P.row_ptr[row0 + r], eb), ee) - eb);
+      hi[h] = (int)(min(max(P.row_ptr[row0 + r + 1], eb), ee) - eb);
       rr[h] = P.R[row0 + r];
     }
   }
@@ -109,29 +81,61 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     const int k = tid + kBlock * j;
     wv[j] = k < wn ? vin[wbase + k] : 0.0;
   }
-  uint32_t c[2][kViUnroll];
-  uint16_t n[2][kViUnroll];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) vi_load(P, lo[h], hi[h], c[h], n[h]);
-#pragma unroll
-  for (int j = 0; j < kViWinPerThread; ++j) {
-    const int k = tid + kBlock * j;
-    if (k < wn) vwin[k] = wv[j];
-  }
-  __syncthreads();
+  const uint32_t ns32 = (uint32_t)P.ns;
   double acc[2] = {0.0, 0.0};
-  for (;;) {
-    bool more = false;
+  bool staged = false;
+  for (int base = 0; base < E; base += kViChunk) {
+    const int ce = min(E - base, kViChunk);
+    // ---- round 2: this chunk's entries, one lane per entry
+    uint32_t cc[kViChunk / kBlock];
+    uint16_t nn[kViChunk / kBlock];
+#pragma unroll
+    for (int j = 0; j < kViChunk / kBlock; ++j) {
+      const int k = tid + kBlock * j;
+      const int64_t e = eb + base + (k < ce ? k : 0);  // a valid index past the end
+      cc[j] = (uint32_t)P.col[e];
+      nn[j] = P.cnt[e];
+    }
+    if (!staged) {  // uniform: the window goes to LDS once per block
+#pragma unroll
+      for (int j = 0; j < kViWinPerThread; ++j) {
+        const int k = tid + kBlock * j;
+        if (k < wn) vwin[k] = wv[j];
+      }
+      staged = true;
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kViChunk / kBlock; ++j) {
+      const int k = tid + kBlock * j;
+      if (k < ce) {
+        double vv = 0.0;
+        if (cc[j] < ns32) {
+          const int64_t w = (int64_t)cc[j] - wbase;
+          vv = (w >= 0 && w < wn) ? vwin[w] : vin[cc[j]];
+        }
+        prod[k] = (double)nn[j] * vv;
+      }
+    }
+    __syncthreads();
+    // ---- each row's products in ascending order (independent LDS reads)
+    const int top = base + ce;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      vi_add(P, vin, vwin, wbase, wn, lo[h], hi[h], c[h], n[h], acc[h]);
-      lo[h] += kViUnroll;
-      more = more || lo[h] < hi[h];
+      int k = max(lo[h], base);
+      const int k1 = min(hi[h], top);
+      for (; k + 4 <= k1; k += 4) {
+        const double x0 = prod[k - base], x1 = prod[k + 1 - base], x2 = prod[k + 2 - base], x3 = prod[k + 3 - base];
+        acc[h] += x0;
+        acc[h] += x1;
+        acc[h] += x2;
+        acc[h] += x3;
+      }
+      for (; k < k1; ++k) acc[h] += prod[k - base];
     }
-    if (!more) break;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) vi_load(P, lo[h], hi[h], c[h], n[h]);
+    __syncthreads();
   }
+  // q aliases the products: every row sum above has completed
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int r = tid + kBlock * h;
