@@ -75,15 +75,23 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     wn = (jw1 - jw0 + 1) * P.nx;  // <= win_rows * nx <= kViWinPerThread * kBlock
     wbase = (int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx;
   }
-  double wv[kViWinPerThread];
+  {
+    // the window goes to LDS before the entries are loaded (their loads need
+    // the block's first row pointer anyway), so its registers are free again
+    double wv[kViWinPerThread];
 #pragma unroll
-  for (int j = 0; j < kViWinPerThread; ++j) {
-    const int k = tid + kBlock * j;
-    wv[j] = k < wn ? vin[wbase + k] : 0.0;
+    for (int j = 0; j < kViWinPerThread; ++j) {
+      const int k = tid + kBlock * j;
+      wv[j] = k < wn ? vin[wbase + k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kViWinPerThread; ++j) {
+      const int k = tid + kBlock * j;
+      if (k < wn) vwin[k] = wv[j];
+    }
   }
   const uint32_t ns32 = (uint32_t)P.ns;
   double acc[2] = {0.0, 0.0};
-  bool staged = false;
   for (int base = 0; base < E; base += kViChunk) {
     const int ce = min(E - base, kViChunk);
     // ---- round 2: this chunk's entries, one lane per entry
@@ -96,15 +104,7 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
       cc[j] = (uint32_t)P.col[e];
       nn[j] = P.cnt[e];
     }
-    if (!staged) {  // uniform: the window goes to LDS once per block
-#pragma unroll
-      for (int j = 0; j < kViWinPerThread; ++j) {
-        const int k = tid + kBlock * j;
-        if (k < wn) vwin[k] = wv[j];
-      }
-      staged = true;
-      __syncthreads();
-    }
+    __syncthreads();  // the window (first round) and the previous round's reads
 #pragma unroll
     for (int j = 0; j < kViChunk / kBlock; ++j) {
       const int k = tid + kBlock * j;
