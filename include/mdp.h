@@ -183,6 +183,21 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
                              void *scratch, size_t scratch_bytes, mdp_vi_stats *stats,
                              void *stream);
 
+/* mdp_value_iterate for n_missions (1..3) distinct missions of one model in
+ * one solve (Sec. II-B update rule per mission). Each sweep reads the model's
+ * transition entries once for all of them; every mission keeps its own values,
+ * residual, sweep count and stopping test, so d_v[i] and stats[i] are exactly
+ * what mdp_value_iterate gives for missions[i] from the same v0 (bit for bit).
+ * d_v: n_missions device pointers, each fp64 [N_s] (v0 in, result out);
+ * stats: n_missions host structs, written when the stream reaches the end of
+ * the solve. scratch: device memory of at least n_missions times
+ * mdp_build_query's scratch_bytes. Errors: MDP_E_INVALID (a mission not built,
+ * repeated missions or value buffers, host pointers), MDP_E_SCRATCH. */
+mdp_status mdp_value_iterate_missions(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
+                                      int32_t n_missions, const int32_t *missions, double tol,
+                                      int32_t max_sweeps, double *const *d_v, void *scratch,
+                                      size_t scratch_bytes, mdp_vi_stats *stats, void *stream);
+
 /* Greedy policy (Sec. II-B): d_pi[s] = the lowest action index attaining
  * max_a R(s,a) + sum_s' P(s'|s,a) v(s'), for every state. d_v fp64 [N_s],
  * d_pi int32 [N_s]. */

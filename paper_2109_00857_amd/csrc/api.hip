@@ -893,6 +893,72 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   return MDP_OK;
 }
 
+mdp_status mdp_value_iterate_missions(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
+                                      int32_t n_missions, const int32_t *missions, double tol, int32_t max_sweeps,
+                                      double *const *d_v, void *scratch, size_t scratch_bytes, mdp_vi_stats *stats,
+                                      void *stream)
+{
+  if (!ctx) return MDP_E_INVALID;
+  if (n_missions < 1 || n_missions > kMaxMissions || !missions || !d_v || !stats || max_sweeps < 0) {
+    set_err(ctx, "n_missions must be in [1, %d]; missions, d_v and stats non-NULL; max_sweeps >= 0", kMaxMissions);
+    return MDP_E_INVALID;
+  }
+  Plan pl;
+  MultiVI M;
+  memset(&M, 0, sizeof(M));
+  M.m = n_missions;
+  for (int i = 0; i < n_missions; ++i) {
+    mdp_status rc = vi_setup(ctx, p, model, missions[i], pl, M.d[i].P);
+    if (rc != MDP_OK) return rc;
+    for (int j = 0; j < i; ++j)
+      if (missions[j] == missions[i] || d_v[j] == d_v[i]) {
+        set_err(ctx, "missions and value buffers must be distinct");
+        return MDP_E_INVALID;
+      }
+    if (!is_device_ptr(d_v[i])) {
+      set_err(ctx, "d_v[%d] must be a device pointer", i);
+      return MDP_E_INVALID;
+    }
+  }
+  const size_t need = (size_t)n_missions * pl.vi_bytes;
+  if (!is_device_ptr(scratch) || scratch_bytes < need) {
+    set_err(ctx, "scratch needs %zu device bytes", need);
+    return MDP_E_SCRATCH;
+  }
+  // [sweep states][stats][per-block residuals][second value buffer per mission]
+  char *sc = (char *)scratch;
+  size_t off = 0;
+  VIState *st = (VIState *)(sc + off);
+  off = align_up(off + sizeof(VIState) * n_missions);
+  mdp_vi_stats *dstats = (mdp_vi_stats *)(sc + off);
+  off = align_up(off + sizeof(mdp_vi_stats) * n_missions);
+  double *wg_res = (double *)(sc + off);
+  off = align_up(off + sizeof(double) * kViGridMaxHost * n_missions);
+  for (int i = 0; i < n_missions; ++i) {
+    BatchVIDesc &d = M.d[i];
+    d.st = d.P.st = st + i;
+    d.P.tol = tol;
+    d.v = d_v[i];
+    d.v_alt = (double *)(sc + off);
+    off = align_up(off + (size_t)d.P.ns * 8);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = launch_vi_init(st, n_missions, s)) != hipSuccess) return hip_fail(ctx, e, "vi init");
+  int n = max_sweeps;
+  if (tol > 0.0) n = std::min(n, p->nt + 1);  // layered: converged after nt + 1 sweeps
+  for (int k = 0; k < n; ++k) {
+    Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
+    if ((e = launch_vi_sweep_missions(M, vi_active_layers(p->nt, k), wg_res, tol, s)) != hipSuccess)
+      return hip_fail(ctx, e, "vi sweep");
+  }
+  if ((e = launch_vi_finish_missions(M, dstats, s)) != hipSuccess) return hip_fail(ctx, e, "vi finish");
+  if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_vi_stats) * n_missions, hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
+    return hip_fail(ctx, e, "vi stats copy");
+  return MDP_OK;
+}
+
 mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
                       const double *d_v, int32_t *d_pi, void *stream)
 {

@@ -204,6 +204,15 @@ struct BatchVIDesc {
 
 constexpr int kMaxBatch = 1024;  // problems per batch
 
+// Missions of one model solved together (every descriptor has the same CSR
+// and shape; rewards, values and sweep states differ). Passed by value.
+constexpr int kMaxMissions = 3;
+struct MultiVI {
+  BatchVIDesc d[kMaxMissions];
+  int m;
+  int pad;
+};
+
 hipError_t launch_vi_init(VIState *st, int n, hipStream_t s);
 // One sweep over layers [0, t_hi) (later layers are final and already in both
 // buffers) and its close; returns the grid used.
@@ -212,6 +221,9 @@ hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, i
 hipError_t launch_vi_sweep_batched(const BatchVIDesc *D, int n, const int64_t *block_start, double *wg_res,
                                    int grid, size_t win_bytes, hipStream_t s);
 hipError_t launch_vi_reset_batched(const BatchVIDesc *D, int n, hipStream_t s);
+// One fused sweep of every mission of V over layers [0, t_hi) and its close.
+hipError_t launch_vi_sweep_missions(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s);
+hipError_t launch_vi_finish_missions(const MultiVI &V, mdp_vi_stats *out, hipStream_t s);
 hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *out, hipStream_t s);
 hipError_t launch_vi_close_batched(const BatchVIDesc *D, int n, int grid, const double *wg_res, double tol,
                                    hipStream_t s);

@@ -1,19 +1,25 @@
 // Value iteration and greedy policy on the CSR model (Sec. II-B update rule).
 //
 // A workgroup takes a block of S cells of one decision layer t (their S * N_a
-// rows are contiguous, at most 512; two rows per thread). Two rounds of
-// global loads per block:
-//   1. the block's entry range, its rows' entry offsets and rewards, each
-//      state's old value, and the window of v_old(t + 1) that the rows can
-//      reach (grid rows within the sub-grid half height of the block's rows);
-//   2. the block's entries (col, cnt), coalesced, one lane per entry.
-// The window goes to LDS; each lane forms cnt * v_old[col] for its entries
-// (the sinks DEAD and TARGET contribute 0) and stages the products in LDS;
-// then each row's thread adds its products in ascending entry order (fp64),
+// rows are contiguous, at most 512; two rows per thread). The block's entry
+// range (its first and one-past-last row pointer) is read with scalar loads
+// while the previous block of the workgroup is processed, so one round of
+// loads per block suffices, all issued together and branch-free:
+//   - its rows' entry offsets and rewards and each state's old value;
+//   - the window of v_old(t + 1) that the rows can reach (grid rows within
+//     the sub-grid half height of the block's rows), copied by the memory
+//     unit straight into LDS (global_load_lds), which costs no registers;
+//   - its entries (col, cnt), coalesced, one lane per entry, up to 2048.
+// Each lane forms cnt * v_old[col] for its entries (a window read in LDS; the
+// sinks DEAD and TARGET contribute 0; a state outside the window, possible
+// only when the window is off, is read from HBM) and stages the products in
+// LDS; then each row's thread adds its products in ascending entry order
+// (fp64),
 //     Q(s, a) = R(s, a) + (sum_k cnt_k * v_old[col_k]) / N_r,
-// and one thread per state takes max_a Q (first maximum on ties). The per-row
-// sum has a fixed order, so every path (single problem, batch, server) gives
-// the same bits.
+// writes Q back to LDS at an odd stride per state, and one thread per state
+// takes max_a Q (first maximum on ties) without bank conflicts. The per-row
+// sum has a fixed order, so every path (single problem, batch, server, several
+// missions at once) gives the same bits.
 //
 // Every transition goes from layer t to layer t + 1 or to a sink, and layer
 // T - 1 reaches only sinks, so after k sweeps the layers t >= T - k hold
@@ -33,13 +39,37 @@
 
 namespace mdpk {
 
-constexpr int kViGridMax = 8192;
+constexpr int kViGridMax = 8192;  // a multiple of kXcds
+constexpr int kXcds = 8;          // compute chiplets (XCDs) of an MI355X
+
+typedef __attribute__((address_space(1))) void *gptr_t;
+typedef __attribute__((address_space(3))) void *lptr_t;
+
+// s_waitcnt vmcnt(0): every vector memory load of this wave has completed,
+// including the copies that write LDS directly.
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Entry range [rb, re) of the block of cells [c0, c0 + S) of layer t, as
+// stored (unclamped): the first and the one-past-last row pointer.
+struct RowSpan {
+  int64_t rb, re;
+};
+
+__device__ inline RowSpan block_span(const VIParams &P, int t, int c0)
+{
+  const int nst = min(P.states_per_wg, P.nc - c0);
+  const int64_t row0 = ((int64_t)t * P.nc + c0) * P.na;
+  // uniform: scalar loads through the constant address space
+  return RowSpan{load_const(P.row_ptr + row0), load_const(P.row_ptr + row0 + (int64_t)nst * P.na)};
+}
 
 // Q of the rows of cells [c0, c0 + S) of layer t, then per state either the
 // new value (returns the block's max |v_new - v_old|) or the first argmax.
+// `span` is the block's entry range (block_span), known before the block
+// starts, so its entries are loaded in the same round as its rows' data.
 template <bool POLICY>
 __device__ inline double vi_block(const VIParams &P, const double *vin, double *vout, int32_t *pi, int t, int c0,
-                                  double *sm, double *vwin)
+                                  RowSpan span, double *sm, double *vwin)
 {
   double *prod = sm + kViProd;
   double *q = sm + kViQ;
@@ -48,25 +78,25 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
   const int nr = nst * P.na;
   const int64_t s0 = (int64_t)t * P.nc + c0;
   const int64_t row0 = s0 * P.na;
-  // ---- round 1. The block's entries [eb, ee), clamped so that a malformed
-  // row pointer can neither read outside col / cnt nor loop long.
-  const int64_t eb = min(max(P.row_ptr[row0], (int64_t)0), P.cap);
-  const int64_t ee = min(min(max(P.row_ptr[row0 + nr], eb), P.cap), eb + (int64_t)nr * P.max_row);
+  // The block's entries [eb, ee), clamped so that a malformed row pointer can
+  // neither read outside col / cnt nor loop long.
+  const int64_t eb = min(max(span.rb, (int64_t)0), P.cap);
+  const int64_t ee = min(min(max(span.re, eb), P.cap), eb + (int64_t)nr * P.max_row);
   const int E = (int)(ee - eb);
-  int lo[2], hi[2];
+  // ---- one round of loads: rows' entry offsets and rewards, own values, the
+  // window of v_old(t + 1), and the first chunk of entries
+  // (branch-free: indices are clamped to valid rows and the results masked
+  // afterwards, so every load of the round is in flight at once)
+  int64_t rlo[2], rhi[2];
   float rr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int r = tid + kBlock * h;
-    lo[h] = hi[h] = 0;
-    rr[h] = 0.0f;
-    if (r < nr) {
-      lo[h] = (int)(min(max(P.row_ptr[row0 + r], eb), ee) - eb);
-      hi[h] = (int)(min(max(P.row_ptr[row0 + r + 1], eb), ee) - eb);
-      rr[h] = P.R[row0 + r];
-    }
+    const int r = min(tid + kBlock * h, nr);
+    rlo[h] = P.row_ptr[row0 + r];
+    rhi[h] = P.row_ptr[row0 + r + (r < nr)];
+    rr[h] = P.R[row0 + min(r, nr - 1)];
   }
-  const double vself = (!POLICY && tid < nst) ? vin[s0 + tid] : 0.0;
+  const double vself = POLICY ? 0.0 : vin[s0 + min(tid, nst - 1)];
   int64_t wbase = 0;
   int wn = 0;
   if (P.win_rows > 0 && t + 1 < P.nt) {
@@ -75,46 +105,75 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     wn = (jw1 - jw0 + 1) * P.nx;  // <= win_rows * nx <= kViWinPerThread * kBlock
     wbase = (int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx;
   }
+  // the window goes straight to LDS (no registers): dword copies, one wave
+  // row of 64 dwords per instruction
   {
-    // the window goes to LDS before the entries are loaded (their loads need
-    // the block's first row pointer anyway), so its registers are free again
-    double wv[kViWinPerThread];
-#pragma unroll
-    for (int j = 0; j < kViWinPerThread; ++j) {
-      const int k = tid + kBlock * j;
-      wv[j] = k < wn ? vin[wbase + k] : 0.0;
+    const int lane = tid & 63, wave = tid >> 6;
+    const char *src = reinterpret_cast<const char *>(vin + wbase);
+    char *dst = reinterpret_cast<char *>(vwin);
+    for (int j = wave * 64; j < 2 * wn; j += kBlock) {
+      if (j + lane < 2 * wn)
+        __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4, 0,
+                                         0);
     }
+  }
+  uint32_t cc[kViChunk / kBlock];
+  uint16_t nn[kViChunk / kBlock];
+  // a model without entries (cap 0) reads its row pointers instead: every
+  // index below is valid, so the loads need no branch
+  const uint32_t *colp = P.cap > 0 ? reinterpret_cast<const uint32_t *>(P.col)
+                                   : reinterpret_cast<const uint32_t *>(P.row_ptr);
+  const uint16_t *cntp = P.cap > 0 ? P.cnt : reinterpret_cast<const uint16_t *>(P.row_ptr);
+  const int64_t elast = max(P.cap - 1, (int64_t)0);
+  auto load_chunk = [&](int base) {
+    const int ce = min(E - base, kViChunk);
 #pragma unroll
-    for (int j = 0; j < kViWinPerThread; ++j) {
+    for (int j = 0; j < kViChunk / kBlock; ++j) {
       const int k = tid + kBlock * j;
-      if (k < wn) vwin[k] = wv[j];
+      const int64_t e = min(eb + base + (k < ce ? k : 0), elast);
+      cc[j] = colp[e];
+      nn[j] = cntp[e];
     }
+  };
+  load_chunk(0);  // unconditional, so that no load waits for another
+  int lo[2], hi[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    lo[h] = (int)(min(max(rlo[h], eb), ee) - eb);
+    hi[h] = (int)(min(max(rhi[h], eb), ee) - eb);
   }
   const uint32_t ns32 = (uint32_t)P.ns;
   double acc[2] = {0.0, 0.0};
   for (int base = 0; base < E; base += kViChunk) {
     const int ce = min(E - base, kViChunk);
-    // ---- round 2: this chunk's entries, one lane per entry
-    uint32_t cc[kViChunk / kBlock];
-    uint16_t nn[kViChunk / kBlock];
+    if (base > 0) load_chunk(base);  // further chunks: one more round each
+    wait_vm();        // this wave's window copies have landed in LDS
+    __syncthreads();  // every wave's, and the previous round's reads are done
+    // v_old of every entry's successor: one LDS read per entry, branch-free
+    // (index 0 outside the window, sinks give 0), then global reads for the
+    // rare states outside the window
+    constexpr int kHalf = kViChunk / kBlock / 2;  // in two halves, to bound registers
 #pragma unroll
-    for (int j = 0; j < kViChunk / kBlock; ++j) {
-      const int k = tid + kBlock * j;
-      const int64_t e = eb + base + (k < ce ? k : 0);  // a valid index past the end
-      cc[j] = (uint32_t)P.col[e];
-      nn[j] = P.cnt[e];
-    }
-    __syncthreads();  // the window (first round) and the previous round's reads
+    for (int j0 = 0; j0 < kViChunk / kBlock; j0 += kHalf) {
+      double vv[kHalf];
+      uint32_t outside = 0;
 #pragma unroll
-    for (int j = 0; j < kViChunk / kBlock; ++j) {
-      const int k = tid + kBlock * j;
-      if (k < ce) {
-        double vv = 0.0;
-        if (cc[j] < ns32) {
-          const int64_t w = (int64_t)cc[j] - wbase;
-          vv = (w >= 0 && w < wn) ? vwin[w] : vin[cc[j]];
-        }
-        prod[k] = (double)nn[j] * vv;
+      for (int j = 0; j < kHalf; ++j) {
+        const int64_t w = (int64_t)cc[j0 + j] - wbase;  // sinks are never inside
+        const bool inw = w >= 0 && w < wn;
+        const double x = vwin[inw ? (int)w : 0];
+        vv[j] = inw ? x : 0.0;
+        outside |= (uint32_t)(!inw && cc[j0 + j] < ns32 && tid + kBlock * (j0 + j) < ce) << j;
+      }
+      if (outside) {
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j)
+          if (outside >> j & 1) vv[j] = vin[cc[j0 + j]];
+      }
+#pragma unroll
+      for (int j = 0; j < kHalf; ++j) {
+        const int k = tid + kBlock * (j0 + j);
+        if (k < ce) prod[k] = (double)nn[j0 + j] * vv[j];
       }
     }
     __syncthreads();
@@ -135,16 +194,19 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     }
     __syncthreads();
   }
-  // q aliases the products: every row sum above has completed
+  // q aliases the products: every row sum above has completed. A state's Q
+  // values sit at an odd stride (N_a, or N_a + 1 when N_a is even), so the
+  // lanes reading one action each of consecutive states hit distinct banks.
+  const int qstride = P.na | 1;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int r = tid + kBlock * h;
-    if (r < nr) q[r] = (double)rr[h] + acc[h] * P.inv_nr;
+    if (r < nr) q[r + (qstride - P.na) * (r / P.na)] = (double)rr[h] + acc[h] * P.inv_nr;
   }
   __syncthreads();
   double d = 0.0;
   if (tid < nst) {
-    const double *qs = q + tid * P.na;
+    const double *qs = q + tid * qstride;
     double best = qs[0];
     int besta = 0;
     for (int a = 1; a < P.na; ++a)
@@ -160,8 +222,51 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
       d = fabs(best - vself);
     }
   }
+  wait_vm();  // no copy into LDS outlives the block (a block without entries never waited)
   __syncthreads();
   return d;
+}
+
+// The blocks of layers [0, t_hi) a workgroup takes. Workgroups are dispatched
+// round-robin over the kXcds chiplets (workgroup w on chiplet w % kXcds), each
+// with its own L2; chiplet x takes the contiguous range x of kXcds equal
+// ranges of the layer-major block order, so a layer's window of v_old(t + 1)
+// is fetched from HBM by (about) one chiplet instead of all of them. Within a
+// range the chiplet's workgroups stride by their count; each block's entry
+// range is loaded while the previous block is processed. Needs gridDim.x to
+// be a multiple of kXcds.
+template <typename F>
+__device__ inline void for_blocks(const VIParams &P, int t_hi, F &&body)
+{
+  const int bpl = P.blocks_per_layer;
+  const int nb = t_hi * bpl;  // < 2^31: the state count fits 32 bits
+  const int x = (int)blockIdx.x % kXcds, nslot = (int)gridDim.x / kXcds;
+  const int b_end = (int)((int64_t)nb * (x + 1) / kXcds);
+  int b = (int)((int64_t)nb * x / kXcds) + (int)blockIdx.x / kXcds;
+  if (b >= b_end) return;
+  const int gq = nslot / bpl, gr = nslot % bpl;
+  int t = b / bpl, c = b - t * bpl;
+  RowSpan span = block_span(P, t, c * P.states_per_wg);
+  for (; b < b_end; b += nslot) {
+    int tn = t + gq, cn = c + gr;
+    if (cn >= bpl) {
+      cn -= bpl;
+      ++tn;
+    }
+    RowSpan nxt{0, 0};
+    if ((int64_t)b + nslot < b_end) nxt = block_span(P, tn, cn * P.states_per_wg);
+    body(t, c * P.states_per_wg, span);
+    t = tn;
+    c = cn;
+    span = nxt;
+  }
+}
+
+// Workgroups of a sweep or policy launch over nb blocks: a multiple of kXcds.
+inline int vi_grid(int64_t nb, int cap)
+{
+  const int64_t g = std::min<int64_t>(std::max<int64_t>(nb, 1), cap);
+  return (int)((g + kXcds - 1) / kXcds * kXcds);
 }
 
 __device__ inline double block_max(double d, double *wmax)
@@ -185,12 +290,9 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep(const VIParams P, const dou
   extern __shared__ double sm[];
   if (P.st->done) return;
   double d = 0.0;
-  const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
-  for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
-    const int t = (int)(blk / P.blocks_per_layer);
-    const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
-    d = fmax(d, vi_block<false>(P, vin, vout, nullptr, t, c0, sm, sm + kViFixed));
-  }
+  for_blocks(P, t_hi, [&](int t, int c0, RowSpan span) {
+    d = fmax(d, vi_block<false>(P, vin, vout, nullptr, t, c0, span, sm, sm + kViFixed));
+  });
   const double m = block_max(d, sm + kViWmax);
   if (threadIdx.x == 0) wg_res[blockIdx.x] = m;
 }
@@ -250,11 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_vi_finish(const VIParams P, double *
 __global__ __launch_bounds__(kBlock) void k_policy(const VIParams P, const double *v, int32_t *pi)
 {
   extern __shared__ double sm[];
-  for (int64_t blk = blockIdx.x; blk < P.n_blocks; blk += gridDim.x) {
-    const int t = (int)(blk / P.blocks_per_layer);
-    const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
-    vi_block<true>(P, v, nullptr, pi, t, c0, sm, sm + kViFixed);
-  }
+  for_blocks(P, P.nt, [&](int t, int c0, RowSpan span) {
+    vi_block<true>(P, v, nullptr, pi, t, c0, span, sm, sm + kViFixed);
+  });
 }
 
 // ------------------------------------------------------------------ batches
@@ -313,7 +413,8 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep_batched(const BatchVIDesc *
     const bool odd = (sd.x & 1) != 0;
     const double *vin = odd ? d.v_alt : d.v;
     double *vout = odd ? d.v : d.v_alt;
-    const double m = block_max(vi_block<false>(P, vin, vout, nullptr, t, c0, sm, vwin), sm + kViWmax);
+    const double m =
+        block_max(vi_block<false>(P, vin, vout, nullptr, t, c0, block_span(P, t, c0), sm, vwin), sm + kViWmax);
     if (tid == 0) res[i] = fmax(res[i], m);
   }
   __syncthreads();
@@ -407,7 +508,242 @@ __global__ __launch_bounds__(kBlock) void k_policy_batched(const BatchVIDesc *D,
     const int64_t blk = g - bstart[i];
     const int t = (int)(blk / P.blocks_per_layer);
     const int c0 = (int)(blk - (int64_t)t * P.blocks_per_layer) * P.states_per_wg;
-    vi_block<true>(P, d.v, nullptr, d.pi, t, c0, sm, vwin);
+    vi_block<true>(P, d.v, nullptr, d.pi, t, c0, block_span(P, t, c0), sm, vwin);
+  }
+}
+
+// ------------------------------------------------------------------ missions
+// Several missions of one model in one sweep. A block's row offsets and
+// entries are read from HBM once, into registers; the missions that have not
+// converged then take turns over them, each with its own window of v_old(t + 1)
+// (copied to LDS at the start), products, row sums (ascending, as in the single
+// sweep), Q at the same odd stride and first argmax. Every mission keeps its
+// own rewards, residual, sweep count (buffer parity) and done flag, so its
+// iterates are those of the single-mission sweep bit for bit.
+template <int M>
+__device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, int t, int c0, RowSpan span,
+                                         double *sm, int win, double *dres)
+{
+  const VIParams &P = V.d[0].P;
+  double *prod = sm;  // products, then Q, of one mission at a time
+  const int tid = threadIdx.x;
+  const int nst = min(P.states_per_wg, P.nc - c0);
+  const int nr = nst * P.na;
+  const int64_t s0 = (int64_t)t * P.nc + c0;
+  const int64_t row0 = s0 * P.na;
+  // this sweep's input and output buffers of mission m (uniform)
+  auto vin = [&](int m) -> const double * { return (odd >> m & 1) ? V.d[m].v_alt : V.d[m].v; };
+  auto vout = [&](int m) -> double * { return (odd >> m & 1) ? V.d[m].v : V.d[m].v_alt; };
+  const int64_t eb = min(max(span.rb, (int64_t)0), P.cap);
+  const int64_t ee = min(min(max(span.re, eb), P.cap), eb + (int64_t)nr * P.max_row);
+  const int E = (int)(ee - eb);
+  // ---- one round of loads, branch-free as in the single sweep
+  int64_t rlo[2], rhi[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = min(tid + kBlock * h, nr);
+    rlo[h] = P.row_ptr[row0 + r];
+    rhi[h] = P.row_ptr[row0 + r + (r < nr)];
+  }
+  float rr[M][2];
+  double vself[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rr[m][h] = V.d[m].P.R[row0 + min(tid + kBlock * h, nr - 1)];
+    vself[m] = vin(m)[s0 + min(tid, nst - 1)];
+  }
+  int64_t wbase = 0;
+  int wn = 0;
+  if (P.win_rows > 0 && t + 1 < P.nt) {
+    const int jw0 = max(0, c0 / P.nx - P.hy);
+    const int jw1 = min(P.ny - 1, (c0 + nst - 1) / P.nx + P.hy);
+    wn = (jw1 - jw0 + 1) * P.nx;  // <= win_rows * nx = win
+    wbase = (int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx;
+  }
+  double *vwin0 = sm + kViFixed;
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!(live >> m & 1)) continue;  // uniform
+      const char *src = reinterpret_cast<const char *>(vin(m) + wbase);
+      char *dst = reinterpret_cast<char *>(vwin0 + m * win);
+      for (int j = wave * 64; j < 2 * wn; j += kBlock) {
+        if (j + lane < 2 * wn)
+          __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4,
+                                           0, 0);
+      }
+    }
+  }
+  uint32_t cc[kViChunk / kBlock];
+  uint16_t nn[kViChunk / kBlock];
+  const uint32_t *colp = P.cap > 0 ? reinterpret_cast<const uint32_t *>(P.col)
+                                   : reinterpret_cast<const uint32_t *>(P.row_ptr);
+  const uint16_t *cntp = P.cap > 0 ? P.cnt : reinterpret_cast<const uint16_t *>(P.row_ptr);
+  const int64_t elast = max(P.cap - 1, (int64_t)0);
+  auto load_chunk = [&](int base) {
+    const int ce = min(E - base, kViChunk);
+#pragma unroll
+    for (int j = 0; j < kViChunk / kBlock; ++j) {
+      const int k = tid + kBlock * j;
+      const int64_t e = min(eb + base + (k < ce ? k : 0), elast);
+      cc[j] = colp[e];
+      nn[j] = cntp[e];
+    }
+  };
+  load_chunk(0);
+  int lo[2], hi[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    lo[h] = (int)(min(max(rlo[h], eb), ee) - eb);
+    hi[h] = (int)(min(max(rhi[h], eb), ee) - eb);
+  }
+  const uint32_t ns32 = (uint32_t)P.ns;
+  double acc[M][2];
+#pragma unroll
+  for (int m = 0; m < M; ++m) acc[m][0] = acc[m][1] = 0.0;
+  for (int base = 0; base < E; base += kViChunk) {
+    const int ce = min(E - base, kViChunk);
+    const int top = base + ce;
+    if (base > 0) load_chunk(base);
+    wait_vm();  // entries, and (first round) this wave's window copies
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!(live >> m & 1)) continue;
+      const double *vw = vwin0 + m * win;
+      __syncthreads();  // every wave's copies; the previous readers of prod
+      constexpr int kHalf = kViChunk / kBlock / 2;
+#pragma unroll
+      for (int j0 = 0; j0 < kViChunk / kBlock; j0 += kHalf) {
+        double vv[kHalf];
+        uint32_t outside = 0;
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j) {
+          const int64_t w = (int64_t)cc[j0 + j] - wbase;  // sinks are never inside
+          const bool inw = w >= 0 && w < wn;
+          const double x = vw[inw ? (int)w : 0];
+          vv[j] = inw ? x : 0.0;
+          outside |= (uint32_t)(!inw && cc[j0 + j] < ns32 && tid + kBlock * (j0 + j) < ce) << j;
+        }
+        if (outside) {
+          const double *src = vin(m);
+#pragma unroll
+          for (int j = 0; j < kHalf; ++j)
+            if (outside >> j & 1) vv[j] = src[cc[j0 + j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j) {
+          const int k = tid + kBlock * (j0 + j);
+          if (k < ce) prod[k] = (double)nn[j0 + j] * vv[j];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int k = max(lo[h], base);
+        const int k1 = min(hi[h], top);
+        for (; k + 4 <= k1; k += 4) {
+          const double x0 = prod[k - base], x1 = prod[k + 1 - base], x2 = prod[k + 2 - base],
+                       x3 = prod[k + 3 - base];
+          acc[m][h] += x0;
+          acc[m][h] += x1;
+          acc[m][h] += x2;
+          acc[m][h] += x3;
+        }
+        for (; k < k1; ++k) acc[m][h] += prod[k - base];
+      }
+    }
+  }
+  const int qstride = P.na | 1;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    dres[m] = 0.0;
+    if (!(live >> m & 1)) continue;
+    __syncthreads();  // the previous readers of prod
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = tid + kBlock * h;
+      if (r < nr) prod[r + (qstride - P.na) * (r / P.na)] = (double)rr[m][h] + acc[m][h] * V.d[m].P.inv_nr;
+    }
+    __syncthreads();
+    if (tid < nst) {
+      const double *qs = prod + tid * qstride;
+      double best = qs[0];
+      for (int a = 1; a < P.na; ++a)
+        if (qs[a] > best) best = qs[a];
+      vout(m)[s0 + tid] = best;
+      dres[m] = fabs(best - vself[m]);
+    }
+  }
+  wait_vm();  // no copy into LDS outlives the block
+  __syncthreads();
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_vi_sweep_missions(const MultiVI V, int t_hi, int win, double *wg_res)
+{
+  extern __shared__ double sm[];
+  int live = 0, odd = 0;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const VIState *st = V.d[m].st;
+    live |= (st->done == 0) << m;
+    odd |= (st->sweeps & 1) << m;
+  }
+  live = __builtin_amdgcn_readfirstlane(live);
+  odd = __builtin_amdgcn_readfirstlane(odd);
+  if (!live) return;  // every mission has converged
+  double d[M], dres[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) d[m] = 0.0;
+  for_blocks(V.d[0].P, t_hi, [&](int t, int c0, RowSpan span) {
+    vi_block_missions<M>(V, live, odd, t, c0, span, sm, win, dres);
+#pragma unroll
+    for (int m = 0; m < M; ++m) d[m] = fmax(d[m], dres[m]);
+  });
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double mx = block_max(d[m], sm + kViWmax);
+    if (threadIdx.x == 0) wg_res[(int64_t)blockIdx.x * M + m] = mx;
+  }
+}
+
+// Close the sweep of each mission (block m), as the batched close.
+__global__ __launch_bounds__(kCloseBlock) void k_vi_close_missions(const MultiVI V, int grid, const double *wg_res,
+                                                                    double tol)
+{
+  __shared__ double wmax[kCloseBlock / 64];
+  const int i = blockIdx.x;
+  VIState *st = V.d[i].st;
+  if (st->done) return;
+  double m = 0.0;
+  for (int w = threadIdx.x; w < grid; w += kCloseBlock) m = fmax(m, wg_res[(int64_t)w * V.m + i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kCloseBlock / 64; ++w) m = fmax(m, wmax[w]);
+    st->sweeps += 1;
+    st->last_res = m;
+    if (m < tol) st->done = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vi_finish_missions(const MultiVI V, mdp_vi_stats *out)
+{
+  const int i = blockIdx.y;
+  const BatchVIDesc &d = V.d[i];
+  const int sweeps = d.st->sweeps;
+  if (sweeps & 1) {
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < d.P.ns; s += (int64_t)gridDim.x * kBlock)
+      d.v[s] = d.v_alt[s];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[i].sweeps = sweeps;
+    out[i].residual = d.st->last_res;
+    out[i].status = d.st->done ? MDP_OK : MDP_E_NOT_CONVERGED;
   }
 }
 
@@ -441,7 +777,7 @@ hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, i
   hipError_t e = allow_lds((const void *)k_vi_sweep, attr);
   if (e != hipSuccess) return e;
   const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nb, std::min(P.n_wg, kViGridMax)));
+  const int grid = vi_grid(nb, std::min(P.n_wg, kViGridMax));
   hipLaunchKernelGGL(k_vi_sweep, dim3(grid), dim3(kBlock), single_lds(P), s, P, vin, vout, t_hi, wg_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_vi_close, dim3(1), dim3(kCloseBlock), 0, s, P, (const double *)wg_res, grid);
@@ -462,7 +798,7 @@ hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStr
   static bool attr = false;
   hipError_t e = allow_lds((const void *)k_policy, attr);
   if (e != hipSuccess) return e;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(P.n_blocks, kViGridMax));
+  const int grid = vi_grid(P.n_blocks, kViGridMax);
   hipLaunchKernelGGL(k_policy, dim3(grid), dim3(kBlock), single_lds(P), s, P, v, pi);
   return hipGetLastError();
 }
@@ -502,6 +838,39 @@ hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *o
 {
   if (n < 1) return hipSuccess;
   hipLaunchKernelGGL(k_vi_status_batched, dim3((n + 63) / 64), dim3(64), 0, s, D, n, out);
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t sweep_missions_t(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s)
+{
+  static bool attr = false;
+  hipError_t e = allow_lds((const void *)k_vi_sweep_missions<M>, attr);
+  if (e != hipSuccess) return e;
+  const VIParams &P = V.d[0].P;
+  const int win = P.win_rows * P.nx;
+  const size_t lds = ((size_t)kViFixed + (size_t)M * win) * 8;
+  const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
+  const int grid = vi_grid(nb, kViGridMax);
+  hipLaunchKernelGGL(k_vi_sweep_missions<M>, dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vi_close_missions, dim3(M), dim3(kCloseBlock), 0, s, V, grid, (const double *)wg_res, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_vi_sweep_missions(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s)
+{
+  switch (V.m) {
+    case 1: return sweep_missions_t<1>(V, t_hi, wg_res, tol, s);
+    case 2: return sweep_missions_t<2>(V, t_hi, wg_res, tol, s);
+    case 3: return sweep_missions_t<3>(V, t_hi, wg_res, tol, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_vi_finish_missions(const MultiVI &V, mdp_vi_stats *out, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_vi_finish_missions, dim3(256, V.m), dim3(kBlock), 0, s, V, out);
   return hipGetLastError();
 }
 

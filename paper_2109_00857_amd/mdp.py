@@ -119,6 +119,9 @@ def load():
             "mdp_build": ([vp, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), vp, C.c_size_t, vp, vp], C.c_int32),
             "mdp_value_iterate": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp,
                                    C.c_size_t, vp, vp], C.c_int32),
+            "mdp_value_iterate_missions": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.POINTER(C.c_int32),
+                                            C.c_double, C.c_int32, C.POINTER(vp), vp, C.c_size_t, vp, vp],
+                                           C.c_int32),
             "mdp_policy": ([vp, P, C.POINTER(MdpModel), C.c_int32, vp, vp, vp], C.c_int32),
             "mdp_batch_query": ([C.c_int32, P, C.c_int64, C.POINTER(C.c_size_t)], C.c_int32),
             "mdp_batch_create": ([vp, C.c_int32, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), vp, vp, vp, C.c_int64,
@@ -151,7 +154,8 @@ def load():
 
 
 EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_error", "mdp_build_query",
-            "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_policy", "mdp_ctx_profile",
+            "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_value_iterate_missions", "mdp_policy",
+            "mdp_ctx_profile",
             "mdp_ctx_profile_read", "mdp_batch_query", "mdp_batch_create", "mdp_batch_build", "mdp_batch_solve",
             "mdp_batch_stats", "mdp_batch_capture", "mdp_batch_replay", "mdp_batch_destroy",
             "mdp_server_footprint", "mdp_server_create", "mdp_server_submit", "mdp_server_step",
@@ -236,6 +240,20 @@ def mdp_value_iterate(ctx, problem: dict, model: dict, mission: int, tol: float,
                                   _ptr(v), _ptr(scratch), scratch.numel(), stats.data_ptr(),
                                   _stream_handle(stream))
     _check(ctx, rc, "mdp_value_iterate")
+
+
+def mdp_value_iterate_missions(ctx, problem: dict, model: dict, missions, tol: float, max_sweeps: int,
+                               vs, scratch: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
+    """Several missions of one model in one solve; ``stats`` holds len(missions) MdpViStats."""
+    n = len(missions)
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    ms = (C.c_int32 * n)(*missions)
+    ptrs = (C.c_void_p * n)(*[_ptr(v) for v in vs])
+    rc = load().mdp_value_iterate_missions(ctx, C.byref(problem_struct(problem)), C.byref(m), n, ms, tol,
+                                           max_sweeps, ptrs, _ptr(scratch), scratch.numel(), stats.data_ptr(),
+                                           _stream_handle(stream))
+    _check(ctx, rc, "mdp_value_iterate_missions")
 
 
 def mdp_policy(ctx, problem: dict, model: dict, mission: int, v: torch.Tensor, pi: torch.Tensor,
@@ -339,6 +357,24 @@ class Planner:
         mdp_value_iterate(self.ctx, problem, model, mission, tol, max_sweeps, v, scratch, st, stream)
         (stream or torch.cuda.current_stream()).synchronize()
         return v, read_stats(st, MdpViStats)
+
+    def value_iterate_missions(self, problem: dict, model: dict, missions, tol: float = 1e-6,
+                               max_sweeps: int = 100000, v0s=None, scratch=None, stream=None):
+        """Returns ([v per mission], [stats per mission]); synchronises the stream."""
+        ns = mdp_build_query(problem)["n_states"]
+        n = len(missions)
+        if v0s is None:
+            vs = [torch.zeros(ns, dtype=torch.float64, device=self.device) for _ in range(n)]
+        else:
+            vs = [v.clone() for v in v0s]
+        if scratch is None:
+            scratch = torch.empty(n * mdp_build_query(problem)["scratch_bytes"], dtype=torch.uint8,
+                                  device=self.device)
+        st = torch.zeros(n * C.sizeof(MdpViStats), dtype=torch.uint8, pin_memory=True)
+        mdp_value_iterate_missions(self.ctx, problem, model, missions, tol, max_sweeps, vs, scratch, st, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        k = C.sizeof(MdpViStats)
+        return vs, [read_stats(st[i * k:(i + 1) * k], MdpViStats) for i in range(n)]
 
     def policy(self, problem: dict, model: dict, mission: int, v: torch.Tensor, stream=None):
         ns = mdp_build_query(problem)["n_states"]

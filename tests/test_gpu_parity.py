@@ -219,3 +219,36 @@ def test_vi_partial_sweeps_and_warm_start(planner, ora):
     assert st_cold["status"] == 0 and st_warm["status"] == 0
     assert st_warm["sweeps"] <= w.problem["nt"] + 1
     assert v_warm.cpu().numpy().tobytes() == v_cold.cpu().numpy().tobytes()
+
+
+def test_vi_missions_fused_equals_single(planner, ora):
+    """One fused solve over several missions of a model gives each mission the
+    values and stats of its own mdp_value_iterate, bit for bit: cold and warm
+    starts, a sweep limit below convergence, and subsets of the missions."""
+    import torch
+
+    w = W.config2(nx=37, ny=29, nt=5, n_real=600)
+    env = planner.upload_env(w)
+    model, stats = planner.build(w.problem, env)
+    assert stats["status"] == 0
+    missions = w.missions()
+    assert len(missions) == 3
+    rng = np.random.default_rng(9)
+    warm = [torch.from_numpy(rng.normal(0.0, 50.0, w.n_states)).to(planner.device) for _ in missions]
+    cases = [(missions, None, 1e-6, 100000), (missions, warm, 1e-6, 100000), (missions, None, 0.0, 3),
+             (missions[1:], None, 1e-6, 100000), (missions[::-1][:2], warm[:2], 1e-6, 100000),
+             (missions[:1], None, 1e-6, 100000)]
+    for ms, v0s, tol, mx in cases:
+        print(f"[parity] fused missions {ms} warm={v0s is not None} tol={tol} max={mx}", flush=True)
+        vs, sts = planner.value_iterate_missions(w.problem, model, ms, tol=tol, max_sweeps=mx, v0s=v0s)
+        for i, m in enumerate(ms):
+            v1, st1 = planner.value_iterate(w.problem, model, m, tol=tol, max_sweeps=mx,
+                                            v0=None if v0s is None else v0s[i])
+            assert sts[i] == st1, (ms, i, sts[i], st1)
+            assert vs[i].cpu().numpy().tobytes() == v1.cpu().numpy().tobytes(), (ms, i)
+    # and the fused values are the oracle's
+    om = ora.build_model(w)
+    vs, _ = planner.value_iterate_missions(w.problem, model, missions)
+    for i, m in enumerate(missions):
+        v_ora, _, w_ora = ora.backward(w, om, m)
+        assert_values_close(vs[i].cpu().numpy(), v_ora, w_ora)
