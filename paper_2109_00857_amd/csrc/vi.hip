@@ -513,6 +513,13 @@ __global__ __launch_bounds__(kBlock) void k_policy_batched(const BatchVIDesc *D,
 }
 
 // ------------------------------------------------------------------ missions
+// Entries per round of the fused sweep: at most kViChunk, at least 1.5 rows
+// per thread (the room Q takes at an odd stride). Small rounds keep registers
+// and LDS (products, one window per mission) low enough for six or seven
+// workgroups per CU; the next round's loads overlap the last mission's sums.
+constexpr int mvi_chunk(int M) { return M == 3 ? 768 : 1024; }
+constexpr int mvi_waves(int M) { return M == 3 ? 7 : (M == 2 ? 6 : 7); }  // per SIMD, the occupancy aimed at
+static_assert(mvi_chunk(3) >= kViRows + kViRows / 2 && mvi_chunk(3) <= kViChunk, "fused chunk size");
 // Several missions of one model in one sweep. A block's row offsets and
 // entries are read from HBM once, into registers; the missions that have not
 // converged then take turns over them, each with its own window of v_old(t + 1)
@@ -524,6 +531,7 @@ template <int M>
 __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, int t, int c0, RowSpan span,
                                          double *sm, int win, double *dres)
 {
+  constexpr int CHM = mvi_chunk(M);
   const VIParams &P = V.d[0].P;
   double *prod = sm;  // products, then Q, of one mission at a time
   const int tid = threadIdx.x;
@@ -546,12 +554,10 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     rhi[h] = P.row_ptr[row0 + r + (r < nr)];
   }
   float rr[M][2];
-  double vself[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) rr[m][h] = V.d[m].P.R[row0 + min(tid + kBlock * h, nr - 1)];
-    vself[m] = vin(m)[s0 + min(tid, nst - 1)];
   }
   int64_t wbase = 0;
   int wn = 0;
@@ -561,7 +567,9 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     wn = (jw1 - jw0 + 1) * P.nx;  // <= win_rows * nx = win
     wbase = (int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx;
   }
-  double *vwin0 = sm + kViFixed;
+  // each mission's window and own old values go straight to LDS
+  double *vwin0 = sm + CHM + 8;       // after the products and the block_max slots
+  double *vself0 = vwin0 + M * win;  // [M][S]
   {
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -574,18 +582,25 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
           __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4,
                                            0, 0);
       }
+      src = reinterpret_cast<const char *>(vin(m) + s0);
+      dst = reinterpret_cast<char *>(vself0 + m * P.states_per_wg);
+      for (int j = wave * 64; j < 2 * nst; j += kBlock) {
+        if (j + lane < 2 * nst)
+          __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4,
+                                           0, 0);
+      }
     }
   }
-  uint32_t cc[kViChunk / kBlock];
-  uint16_t nn[kViChunk / kBlock];
+  uint32_t cc[CHM / kBlock];
+  uint16_t nn[CHM / kBlock];
   const uint32_t *colp = P.cap > 0 ? reinterpret_cast<const uint32_t *>(P.col)
                                    : reinterpret_cast<const uint32_t *>(P.row_ptr);
   const uint16_t *cntp = P.cap > 0 ? P.cnt : reinterpret_cast<const uint16_t *>(P.row_ptr);
   const int64_t elast = max(P.cap - 1, (int64_t)0);
   auto load_chunk = [&](int base) {
-    const int ce = min(E - base, kViChunk);
+    const int ce = min(E - base, CHM);
 #pragma unroll
-    for (int j = 0; j < kViChunk / kBlock; ++j) {
+    for (int j = 0; j < CHM / kBlock; ++j) {
       const int k = tid + kBlock * j;
       const int64_t e = min(eb + base + (k < ce ? k : 0), elast);
       cc[j] = colp[e];
@@ -603,19 +618,23 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
   double acc[M][2];
 #pragma unroll
   for (int m = 0; m < M; ++m) acc[m][0] = acc[m][1] = 0.0;
-  for (int base = 0; base < E; base += kViChunk) {
-    const int ce = min(E - base, kViChunk);
+  // With the last mission iterating, the next chunk's loads are issued once
+  // its products are formed (the chunk's entries are used up), overlapping
+  // its sums; otherwise at the top of the next round.
+  const bool early = (live >> (M - 1) & 1) != 0;
+  for (int base = 0; base < E; base += CHM) {
+    const int ce = min(E - base, CHM);
     const int top = base + ce;
-    if (base > 0) load_chunk(base);
-    wait_vm();  // entries, and (first round) this wave's window copies
+    if (base > 0 && !early) load_chunk(base);
+    wait_vm();  // this chunk's entries, and (first round) this wave's copies
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!(live >> m & 1)) continue;
       const double *vw = vwin0 + m * win;
       __syncthreads();  // every wave's copies; the previous readers of prod
-      constexpr int kHalf = kViChunk / kBlock / 2;
+      constexpr int kHalf = CHM / kBlock / 2;
 #pragma unroll
-      for (int j0 = 0; j0 < kViChunk / kBlock; j0 += kHalf) {
+      for (int j0 = 0; j0 < CHM / kBlock; j0 += kHalf) {
         double vv[kHalf];
         uint32_t outside = 0;
 #pragma unroll
@@ -638,6 +657,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
           if (k < ce) prod[k] = (double)nn[j0 + j] * vv[j];
         }
       }
+      if (m == M - 1 && top < E) load_chunk(top);  // (mission M - 1 is live: early)
       __syncthreads();
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -656,11 +676,12 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     }
   }
   const int qstride = P.na | 1;
+  wait_vm();  // the own-value copies (a block without entries has not waited yet)
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     dres[m] = 0.0;
     if (!(live >> m & 1)) continue;
-    __syncthreads();  // the previous readers of prod
+    __syncthreads();  // the previous readers of prod; every wave's copies
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int r = tid + kBlock * h;
@@ -673,7 +694,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
       for (int a = 1; a < P.na; ++a)
         if (qs[a] > best) best = qs[a];
       vout(m)[s0 + tid] = best;
-      dres[m] = fabs(best - vself[m]);
+      dres[m] = fabs(best - vself0[m * P.states_per_wg + tid]);
     }
   }
   wait_vm();  // no copy into LDS outlives the block
@@ -681,7 +702,8 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
 }
 
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_vi_sweep_missions(const MultiVI V, int t_hi, int win, double *wg_res)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mvi_waves(M), 8))) void k_vi_sweep_missions(
+    const MultiVI V, int t_hi, int win, double *wg_res)
 {
   extern __shared__ double sm[];
   int live = 0, odd = 0;
@@ -704,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep_missions(const MultiVI V, i
   });
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-    const double mx = block_max(d[m], sm + kViWmax);
+    const double mx = block_max(d[m], sm + mvi_chunk(M));
     if (threadIdx.x == 0) wg_res[(int64_t)blockIdx.x * M + m] = mx;
   }
 }
@@ -849,7 +871,7 @@ static hipError_t sweep_missions_t(const MultiVI &V, int t_hi, double *wg_res, d
   if (e != hipSuccess) return e;
   const VIParams &P = V.d[0].P;
   const int win = P.win_rows * P.nx;
-  const size_t lds = ((size_t)kViFixed + (size_t)M * win) * 8;
+  const size_t lds = ((size_t)mvi_chunk(M) + 8 + (size_t)M * (win + P.states_per_wg)) * 8;
   const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
   const int grid = vi_grid(nb, kViGridMax);
   hipLaunchKernelGGL(k_vi_sweep_missions<M>, dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
