@@ -1177,11 +1177,20 @@ hipError_t plan_build_groups(std::vector<std::pair<double, BatchItem>> &items, c
 // Enqueue the persistent launches of a batched build (after its init kernel):
 // one per group, or, when item_cost is given, consecutive chunks of at most
 // max_cost each (so that work on other streams can run between them).
-hipError_t enqueue_build_groups(mdp_ctx *ctx, const BatchBuildDesc *D, const BatchItem *d_items,
-                                const std::vector<BuildGroup> &groups, unsigned int *counters, uint64_t *pool,
-                                unsigned long long *pool_top, int64_t pool_cap, hipStream_t s,
-                                const std::vector<double> *item_cost = nullptr, double max_cost = 0.0)
+// One persistent launch over items [first, first + count) of a group.
+struct BuildLaunch {
+  int first = 0, count = 0, kmax = 4, grid = 1, counter = 0;
+  bool near = false;
+  size_t lds = 0;
+};
+
+// The launches of a work list: one per group, or, with item costs and
+// max_cost > 0, runs of consecutive items of at most max_cost each (while
+// launch counters last).
+std::vector<BuildLaunch> plan_build_launches(const std::vector<BuildGroup> &groups,
+                                             const std::vector<double> *item_cost = nullptr, double max_cost = 0.0)
 {
+  std::vector<BuildLaunch> out;
   int launch = 0;
   for (size_t g = 0; g < groups.size(); ++g) {
     const BuildGroup &G = groups[g];
@@ -1195,13 +1204,37 @@ hipError_t enqueue_build_groups(mdp_ctx *ctx, const BatchBuildDesc *D, const Bat
         while (k1 < end && (k1 == k || c + (*item_cost)[k1] <= max_cost)) c += (*item_cost)[k1++];
       }
       if (launch == kMaxBuildLaunches - 1) k1 = end;  // the last counter takes the rest
-      Timed tm(ctx, MDP_KERNEL_BUILD, s);
-      hipError_t e = launch_batch_build(D, d_items + k, k1 - k, counters + launch, pool, pool_top, pool_cap, G.kmax,
-                                        G.near, G.lds, std::min(G.grid, k1 - k), s);
-      if (e != hipSuccess) return e;
-      ++launch;
+      BuildLaunch b;
+      b.first = k;
+      b.count = k1 - k;
+      b.kmax = G.kmax;
+      b.near = G.near;
+      b.lds = G.lds;
+      b.grid = std::min(G.grid, k1 - k);
+      b.counter = launch++;
+      out.push_back(b);
       k = k1;
     }
+  }
+  return out;
+}
+
+hipError_t enqueue_build_launch(mdp_ctx *ctx, const BatchBuildDesc *D, const BatchItem *d_items, const BuildLaunch &b,
+                                unsigned int *counters, uint64_t *pool, unsigned long long *pool_top,
+                                int64_t pool_cap, hipStream_t s)
+{
+  Timed tm(ctx, MDP_KERNEL_BUILD, s);
+  return launch_batch_build(D, d_items + b.first, b.count, counters + b.counter, pool, pool_top, pool_cap, b.kmax,
+                            b.near, b.lds, b.grid, s);
+}
+
+hipError_t enqueue_build_groups(mdp_ctx *ctx, const BatchBuildDesc *D, const BatchItem *d_items,
+                                const std::vector<BuildGroup> &groups, unsigned int *counters, uint64_t *pool,
+                                unsigned long long *pool_top, int64_t pool_cap, hipStream_t s)
+{
+  for (const BuildLaunch &b : plan_build_launches(groups)) {
+    hipError_t e = enqueue_build_launch(ctx, D, d_items, b, counters, pool, pool_top, pool_cap, s);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1573,6 +1606,7 @@ ReqSizes req_sizes(const mdp_problem *p, const Plan &pl)
 
 struct ServeReq {
   int64_t tag = 0;
+  int64_t seq = 0;  // submission order
   mdp_problem p{};
   mdp_env env{};
   int mission = 0;
@@ -1628,9 +1662,11 @@ struct Pinned {
 // large requests use different lanes, so a small build never waits for a
 // large one (each large build is split into short launches that the small
 // lane's and the sweeps' kernels interleave with).
+constexpr int kServeAhead = 2;  // build launches of a lane in flight at once
+
 struct BuildLane {
   hipStream_t stream = nullptr;
-  hipEvent_t event = nullptr;       // end of the batch in flight
+  hipEvent_t event = nullptr;       // end of the batch in flight (recorded with its tail)
   std::vector<ServeReq *> building; // the batch in flight
   Block blk;                        // its scratch and staging block
   BatchBuildDesc *d_bdesc = nullptr;
@@ -1638,6 +1674,20 @@ struct BuildLane {
   BatchItem *d_items = nullptr;
   size_t items_cap = 0;
   Pinned h_bdesc, h_items, h_tabs, h_bstat;
+  // The batch's build launches are enqueued a few at a time (serve_pump), so
+  // that sweeps enqueued meanwhile on other streams reach the GPU between
+  // them instead of behind the whole build.
+  std::vector<BuildLaunch> plan;
+  size_t next = 0;
+  hipEvent_t ahead[kServeAhead] = {};
+  int ahead_head = 0, ahead_n = 0;
+  bool tail = false;  // scan, copy, statistics and `event` enqueued
+  unsigned int *counter = nullptr;
+  uint64_t *pool = nullptr;
+  unsigned long long *pool_top = nullptr;
+  int64_t pool_cap = 0;
+  int n_items = 0;
+  mdp_build_stats *bstats = nullptr;
 };
 
 constexpr int kServeLanes = 2;  // 0: small builds, 1: large builds
@@ -1653,6 +1703,8 @@ struct mdp_server {
   std::vector<ServeReq *> running;  // built; swept on the caller's stream
   std::vector<mdp_served> done;     // completion records not yet polled
   int64_t step_no = 0;
+  int64_t n_submitted = 0;
+  hipEvent_t sync_ev = nullptr;  // end of a step's work on the caller's stream
   // device tables, sized for cfg.max_inflight problems
   BatchVIDesc *d_vrun = nullptr, *d_vret = nullptr;
   int64_t *d_bs_ret = nullptr;
@@ -1674,14 +1726,17 @@ namespace {
 void serve_free_all(mdp_server *S)
 {
   for (BuildLane &L : S->lane) {
-    if (L.event && !L.building.empty()) (void)hipEventSynchronize(L.event);
+    if (L.stream && !L.building.empty()) (void)hipStreamSynchronize(L.stream);
     for (ServeReq *r : L.building) delete r;
+    for (hipEvent_t ev : L.ahead)
+      if (ev) (void)hipEventDestroy(ev);
     void *bufs[] = {L.d_bdesc, L.d_tabs, L.d_items};
     for (void *p : bufs)
       if (p) (void)hipFree(p);
     if (L.event) (void)hipEventDestroy(L.event);
     if (L.stream) (void)hipStreamDestroy(L.stream);
   }
+  if (S->sync_ev) (void)hipEventDestroy(S->sync_ev);
   for (ServeReq *r : S->queue) delete r;
   for (ServeReq *r : S->running) delete r;
   void *bufs[] = {S->d_vrun, S->d_vret, S->d_bs_ret, S->d_bs_sweeps, S->d_wg_res, S->d_vstat};
@@ -1758,6 +1813,8 @@ constexpr double kServeWorkRatio = 4.0;
 // Requests above this build cost use the large-build lane (a paper-shaped
 // 100 x 100 x 120 request with 5000 realizations and 16 headings is ~1.1e11).
 constexpr double kServeLargeCost = 3e10;
+// Longest a step waits for a build when it has nothing to sweep.
+constexpr int kServeWaitUs = 500;
 
 double build_cost(const ServeReq *r)
 {
@@ -1772,10 +1829,64 @@ size_t build_block_bytes(const std::vector<ServeReq *> &fresh)
   return b;
 }
 
-// Enqueue the batched build of the requests in L.building on the lane's
-// stream: descriptors through pinned staging, the persistent launches (in
-// short chunks), scan, copy and statistics (copied to pinned memory), then the
-// batch's event.
+// Keep the lane's build going: enqueue its next launches while fewer than
+// kServeAhead are in flight, then, after the last one, the batch's tail (scan,
+// copy, statistics into pinned memory, the batch's event).
+mdp_status serve_pump(mdp_server *S, BuildLane &L)
+{
+  hipStream_t s = L.stream;
+  hipError_t e;
+  while (L.next < L.plan.size()) {
+    if (L.ahead_n == kServeAhead) {
+      const hipError_t q = hipEventQuery(L.ahead[L.ahead_head]);
+      if (q == hipErrorNotReady) return MDP_OK;
+      if (q != hipSuccess) return hip_fail(S->ctx, q, "serve build");
+      L.ahead_head = (L.ahead_head + 1) % kServeAhead;
+      --L.ahead_n;
+    }
+    if ((e = enqueue_build_launch(S->ctx, L.d_bdesc, L.d_items, L.plan[L.next], L.counter, L.pool, L.pool_top,
+                                  L.pool_cap, s)) != hipSuccess ||
+        (e = hipEventRecord(L.ahead[(L.ahead_head + L.ahead_n) % kServeAhead], s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve build");
+    ++L.ahead_n;
+    ++L.next;
+  }
+  if (L.tail) return MDP_OK;
+  const int n = (int)L.building.size();
+  if ((e = launch_batch_scan(L.d_bdesc, n, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve scan");
+  {
+    Timed tm(S->ctx, MDP_KERNEL_COPY, s);
+    if ((e = launch_batch_copy(L.d_bdesc, L.d_items, L.n_items, L.pool, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve copy");
+  }
+  if ((e = launch_batch_finalize(L.d_bdesc, n, L.bstats, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve finalize");
+  if ((e = hipMemcpyAsync(L.h_bstat.p, L.bstats, sizeof(mdp_build_stats) * n, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipEventRecord(L.event, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve build end");
+  L.tail = true;
+  return MDP_OK;
+}
+
+// Wait for the work enqueued so far on stream s, keeping the build lanes fed
+// meanwhile.
+hipError_t serve_wait(mdp_server *S, hipStream_t s)
+{
+  hipError_t e = hipEventRecord(S->sync_ev, s);
+  if (e != hipSuccess) return e;
+  for (;;) {
+    e = hipEventQuery(S->sync_ev);
+    if (e != hipErrorNotReady) return e;
+    for (BuildLane &L : S->lane)
+      if (!L.building.empty() && serve_pump(S, L) != MDP_OK) return hipErrorUnknown;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+// Start the batched build of the requests in L.building on the lane's stream:
+// descriptors through pinned staging, the work counters, then the persistent
+// launches in short chunks, a few at a time (serve_pump).
 mdp_status serve_build(mdp_server *S, BuildLane &L, char *blk)
 {
   const std::vector<ServeReq *> &fresh = L.building;
@@ -1856,22 +1967,17 @@ mdp_status serve_build(mdp_server *S, BuildLane &L, char *blk)
     return hip_fail(S->ctx, e, "serve descriptors");
   if ((e = launch_batch_build_init(L.d_bdesc, n, counter, pool_top, s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve build init");
-  if ((e = enqueue_build_groups(S->ctx, L.d_bdesc, L.d_items, groups, counter, pool, pool_top, pool_cap, s, &cost,
-                                 kServeChunkCost)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve build");
-  if ((e = launch_batch_scan(L.d_bdesc, n, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve scan");
-  {
-    Timed tm(S->ctx, MDP_KERNEL_COPY, s);
-    if ((e = launch_batch_copy(L.d_bdesc, L.d_items, (int)flat.size(), pool, s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve copy");
-  }
-  if ((e = launch_batch_finalize(L.d_bdesc, n, bstats, s)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve finalize");
-  if ((e = hipMemcpyAsync(L.h_bstat.p, bstats, sizeof(mdp_build_stats) * n, hipMemcpyDeviceToHost, s)) !=
-          hipSuccess ||
-      (e = hipEventRecord(L.event, s)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve build end");
-  return MDP_OK;
+  L.plan = plan_build_launches(groups, &cost, kServeChunkCost);
+  L.next = 0;
+  L.ahead_head = L.ahead_n = 0;
+  L.tail = false;
+  L.counter = counter;
+  L.pool = pool;
+  L.pool_top = pool_top;
+  L.pool_cap = pool_cap;
+  L.n_items = (int)flat.size();
+  L.bstats = bstats;
+  return serve_pump(S, L);
 }
 
 // The build batch has finished: record its statistics, give back the unused
@@ -1997,12 +2103,15 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
   for (BuildLane &L : S->lane)
     if ((e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&L.event, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&L.ahead[0], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&L.ahead[1], hipEventDisableTiming)) != hipSuccess ||
         (e = hipMalloc((void **)&L.d_bdesc, sizeof(BatchBuildDesc) * n)) != hipSuccess ||
         (e = hipMalloc((void **)&L.d_tabs, sizeof(float) * 2 * kMaxA * n)) != hipSuccess) {
       serve_free_all(S);
       return hip_fail(ctx, e, "server build lanes");
     }
-  if ((e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
+  if ((e = hipEventCreateWithFlags(&S->sync_ev, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vret, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_bs_ret, sizeof(int64_t) * (n + 1))) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_bs_sweeps, sizeof(int64_t) * (n + 1) * nt)) != hipSuccess ||
@@ -2059,6 +2168,7 @@ mdp_status mdp_server_submit(mdp_server *S, const mdp_problem *p, const mdp_env 
   r->limit = S->cfg.max_sweeps;
   if (S->cfg.tol > 0.0) r->limit = std::min(r->limit, r->p.nt + 1);
   r->res.tag = tag;
+  r->seq = S->n_submitted++;
   S->queue.push_back(r);
   return MDP_OK;
 }
@@ -2071,11 +2181,20 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   mdp_status rc;
   ++S->step_no;
   // ---- finished build batches join the sweeps; idle lanes admit new batches
+  // With nothing to sweep, a step waits for a build to finish, but at most
+  // kServeWaitUs: the caller gets control back to submit new arrivals (which
+  // an idle lane can start building at once) and calls step again.
   auto poll_lanes = [&](bool wait) -> mdp_status {
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::microseconds(kServeWaitUs);
     for (;;) {
       bool joined = false, busy = false;
       for (BuildLane &L : S->lane) {
         if (L.building.empty()) continue;
+        if (mdp_status pr = serve_pump(S, L); pr != MDP_OK) return pr;
+        if (!L.tail) {
+          busy = true;
+          continue;
+        }
         hipError_t q = hipEventQuery(L.event);
         if (q == hipSuccess) {
           serve_join(S, L);
@@ -2086,7 +2205,7 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
           return hip_fail(S->ctx, q, "serve build");
         }
       }
-      if (joined || !busy || !wait) return MDP_OK;
+      if (joined || !busy || !wait || std::chrono::steady_clock::now() >= t_end) return MDP_OK;
       std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
   };
@@ -2106,20 +2225,23 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
     if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building());
     return MDP_OK;
   }
-  // ---- sweeps, shortest remaining work first: this step sweeps the built
-  // requests whose remaining work (rows times sweeps still to run) is within
-  // kServeWorkRatio of the smallest; the others wait (their state is untouched)
+  // ---- sweeps, shortest remaining work first, without starving the oldest:
+  // this step sweeps the built requests whose remaining work (rows times
+  // sweeps still to run) is within kServeWorkRatio of the smallest, and the
+  // earliest-submitted built request in any case; the others wait (their
+  // state is untouched)
   std::vector<ServeReq *> sweep, paused;
   {
     double wmin = 0.0;
-    bool first = true;
+    const ServeReq *oldest = nullptr;
     for (ServeReq *r : S->running) {
       const double w = (double)r->z.rows * (r->limit - r->sweeps);
-      if (first || w < wmin) wmin = w;
-      first = false;
+      if (!oldest || w < wmin) wmin = w;
+      if (!oldest || r->seq < oldest->seq) oldest = r;
     }
     for (ServeReq *r : S->running)
-      ((double)r->z.rows * (r->limit - r->sweeps) <= kServeWorkRatio * wmin ? sweep : paused).push_back(r);
+      (r == oldest || (double)r->z.rows * (r->limit - r->sweeps) <= kServeWorkRatio * wmin ? sweep : paused)
+          .push_back(r);
   }
   S->running = sweep;
   struct KeepPaused {  // paused requests return to the running set on every exit
@@ -2164,7 +2286,7 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   mdp_vi_stats *hv = S->h_vstat.as<mdp_vi_stats>();
   if ((e = launch_vi_status_batched(S->d_vrun, n_run, S->d_vstat, s)) != hipSuccess ||
       (e = hipMemcpyAsync(hv, S->d_vstat, sizeof(mdp_vi_stats) * n_run, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
+      (e = serve_wait(S, s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve vi stats");
   // ---- retire converged requests (and failed builds)
   std::vector<ServeReq *> ret, keep;
@@ -2205,7 +2327,7 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
         return hip_fail(S->ctx, e, "serve results");
     }
     if ((e = hipMemcpyAsync(hf, S->d_vstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
+        (e = serve_wait(S, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve retire");
     for (int i = 0; i < n; ++i) {
       ServeReq *r = ret[i];
