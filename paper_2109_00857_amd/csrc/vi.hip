@@ -49,6 +49,27 @@ typedef __attribute__((address_space(3))) void *lptr_t;
 // including the copies that write LDS directly.
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// First maximum of qs[0 .. na): the largest value and the lowest index
+// attaining it. Reads go out in groups of 8 independent LDS loads (indices
+// past na repeat qs[na - 1], which a strict comparison never takes).
+__device__ inline double first_max(const double *qs, int na, int &besta)
+{
+  double best = qs[0];
+  besta = 0;
+  for (int a0 = 0; a0 < na; a0 += 8) {
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = qs[min(a0 + j, na - 1)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (x[j] > best) {  // the lowest index wins ties
+        best = x[j];
+        besta = a0 + j;
+      }
+  }
+  return best;
+}
+
 // Entry range [rb, re) of the block of cells [c0, c0 + S) of layer t, as
 // stored (unclamped): the first and the one-past-last row pointer.
 struct RowSpan {
@@ -206,14 +227,8 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
   __syncthreads();
   double d = 0.0;
   if (tid < nst) {
-    const double *qs = q + tid * qstride;
-    double best = qs[0];
     int besta = 0;
-    for (int a = 1; a < P.na; ++a)
-      if (qs[a] > best) {  // the lowest index wins ties
-        best = qs[a];
-        besta = a;
-      }
+    const double best = first_max(q + tid * qstride, P.na, besta);
     const int64_t s = s0 + tid;
     if (POLICY) {
       pi[s] = besta;
@@ -689,10 +704,8 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     }
     __syncthreads();
     if (tid < nst) {
-      const double *qs = prod + tid * qstride;
-      double best = qs[0];
-      for (int a = 1; a < P.na; ++a)
-        if (qs[a] > best) best = qs[a];
+      int besta;
+      const double best = first_max(prod + tid * qstride, P.na, besta);
       vout(m)[s0 + tid] = best;
       dres[m] = fabs(best - vself0[m * P.states_per_wg + tid]);
     }

@@ -252,3 +252,37 @@ def test_vi_missions_fused_equals_single(planner, ora):
     for i, m in enumerate(missions):
         v_ora, _, w_ora = ora.backward(w, om, m)
         assert_values_close(vs[i].cpu().numpy(), v_ora, w_ora)
+
+
+def test_vi_missions_rejects_bad_arguments(planner):
+    """Argument errors of the fused solve come back synchronously as MDP_E_INVALID
+    (or MDP_E_SCRATCH) and enqueue nothing."""
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    w = W.config1(nt=3, n_real=100, sub_h=3)
+    w.problem["mission_mask"] = 0b011  # missions 0 and 1 built
+    model, stats = planner.build(w.problem, planner.upload_env(w))
+    assert stats["status"] == 0
+    ns = w.n_states
+    sc = torch.empty(3 * mdp.mdp_build_query(w.problem)["scratch_bytes"], dtype=torch.uint8,
+                     device=planner.device)
+    st = torch.zeros(3 * mdp.C.sizeof(mdp.MdpViStats), dtype=torch.uint8, pin_memory=True)
+    vs = [torch.zeros(ns, dtype=torch.float64, device=planner.device) for _ in range(4)]
+    cases = [([], mdp.MDP_E_INVALID),                  # no mission
+             ([0, 1, 0, 1], mdp.MDP_E_INVALID),        # more than three
+             ([0, 0], mdp.MDP_E_INVALID),              # repeated mission
+             ([0, 2], mdp.MDP_E_INVALID)]              # mission 2 was not built
+    for ms, want in cases:
+        with pytest.raises(mdp.MdpError) as e:
+            mdp.mdp_value_iterate_missions(planner.ctx, w.problem, model, ms, 1e-6, 100, vs[:len(ms)], sc, st)
+        assert e.value.status == want, (ms, e.value)
+    with pytest.raises(mdp.MdpError) as e:  # one value buffer for two missions
+        mdp.mdp_value_iterate_missions(planner.ctx, w.problem, model, [0, 1], 1e-6, 100, [vs[0], vs[0]], sc, st)
+    assert e.value.status == mdp.MDP_E_INVALID
+    with pytest.raises(mdp.MdpError) as e:  # scratch for one mission only
+        mdp.mdp_value_iterate_missions(planner.ctx, w.problem, model, [0, 1], 1e-6, 100, vs[:2], sc[:1024], st)
+    assert e.value.status == mdp.MDP_E_SCRATCH
+    vs2, sts = planner.value_iterate_missions(w.problem, model, [1, 0])
+    assert all(s["status"] == 0 for s in sts)
