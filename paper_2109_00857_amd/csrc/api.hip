@@ -155,7 +155,7 @@ const char *make_plan(const mdp_problem *p, Plan &pl, const PlanChoice *choice =
   pl.W = 2 * p->sub_hx + 1;
   pl.nsg = pl.W * (2 * p->sub_hy + 1);
   pl.rows = (int64_t)p->nt * pl.nc * pl.na;
-  pl.kmax = p->n_modes <= 4 ? 4 : (p->n_modes <= 8 ? 8 : (p->n_modes <= 12 ? 12 : 16));
+  pl.kmax = mode_bound(p->n_modes);
   bool ok = false;
   if (choice) {
     const int rl = choice->row_lanes;
@@ -231,7 +231,7 @@ TuneKey tune_key(const mdp_problem *p)
   k.na = p->n_head * p->n_speed;
   k.W = 2 * p->sub_hx + 1;
   k.H = 2 * p->sub_hy + 1;
-  k.kmax = p->n_modes <= 4 ? 4 : (p->n_modes <= 8 ? 8 : (p->n_modes <= 12 ? 12 : 16));
+  k.kmax = mode_bound(p->n_modes);
   k.near = (p->flags & MDP_FLAG_NEAR_EDGE) ? 1 : 0;
   k.nr_log2 = lg(p->n_real);
   k.nc_log2 = lg((int64_t)p->nx * p->ny);

@@ -793,9 +793,13 @@ hipError_t launch_build_slab(const BuildParams &P, const SlabParams &S, int kmax
                              size_t lds, hipStream_t s)
 {
   switch (kmax) {
+    case 2: return launch_build_k<2>(P, S, pack16, near, lds, s);
     case 4: return launch_build_k<4>(P, S, pack16, near, lds, s);
+    case 6: return launch_build_k<6>(P, S, pack16, near, lds, s);
     case 8: return launch_build_k<8>(P, S, pack16, near, lds, s);
+    case 10: return launch_build_k<10>(P, S, pack16, near, lds, s);
     case 12: return launch_build_k<12>(P, S, pack16, near, lds, s);
+    case 14: return launch_build_k<14>(P, S, pack16, near, lds, s);
     default: return launch_build_k<16>(P, S, pack16, near, lds, s);
   }
 }
@@ -816,9 +820,13 @@ static const void *batch_kernel()
 static const void *batch_kernel_for(int kmax, bool near)
 {
   switch (kmax) {
+    case 2: return near ? batch_kernel<2, true>() : batch_kernel<2, false>();
     case 4: return near ? batch_kernel<4, true>() : batch_kernel<4, false>();
+    case 6: return near ? batch_kernel<6, true>() : batch_kernel<6, false>();
     case 8: return near ? batch_kernel<8, true>() : batch_kernel<8, false>();
+    case 10: return near ? batch_kernel<10, true>() : batch_kernel<10, false>();
     case 12: return near ? batch_kernel<12, true>() : batch_kernel<12, false>();
+    case 14: return near ? batch_kernel<14, true>() : batch_kernel<14, false>();
     default: return near ? batch_kernel<16, true>() : batch_kernel<16, false>();
   }
 }

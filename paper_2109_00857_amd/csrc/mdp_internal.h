@@ -204,6 +204,10 @@ struct BatchVIDesc {
 
 constexpr int kMaxBatch = 1024;  // problems per batch
 
+// Mode terms a build kernel is compiled for: K rounded up to even (2..16);
+// the terms past K have zero coefficients and leave the sums unchanged.
+inline int mode_bound(int k) { return k <= 2 ? 2 : (k >= 16 ? 16 : (k + 1) & ~1); }
+
 // Missions of one model solved together (every descriptor has the same CSR
 // and shape; rewards, values and sweep states differ). Passed by value.
 constexpr int kMaxMissions = 3;
