@@ -678,6 +678,7 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
 // of them for kTuneTiles cell tiles of the default shape (many waves of
 // resident workgroups, so the timing is the steady state, not the tail).
 static constexpr double kTuneTiles = 16384;
+static constexpr int kTuneRounds = 4;  // timed rounds over all candidates
 
 static const char *tune_sample(const mdp_problem *p, mdp_problem &q)
 {
@@ -767,15 +768,17 @@ mdp_status mdp_autotune(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, 
   const bool prof = ctx->profiling;
   ctx->profiling = false;
   mdp_status rc = MDP_OK;
-  int best = -1;
-  for (size_t i = 0; i < cands.size() && rc == MDP_OK; ++i) {
-    Plan pl;
-    make_plan(&q, pl, &cands[i]);
-    mdp_build_stats st;
-    double ms_best = 1e30;
-    for (int rep = 0; rep < 3 && rc == MDP_OK; ++rep) {  // first run warms up
+  // Round robin over the candidates, kTuneRounds times after one warm-up
+  // round; each keeps its fastest time (drift of clocks over the sweep hits
+  // every candidate alike).
+  std::vector<Plan> plans(cands.size());
+  std::vector<double> ms_best(cands.size(), 1e30);
+  for (size_t i = 0; i < cands.size(); ++i) make_plan(&q, plans[i], &cands[i]);
+  for (int round = 0; round <= kTuneRounds && rc == MDP_OK; ++round) {
+    for (size_t i = 0; i < cands.size() && rc == MDP_OK; ++i) {
+      mdp_build_stats st;
       if ((e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(ctx, e, "autotune record");
-      if (rc == MDP_OK) rc = build_with_plan(ctx, &q, env, &M, sc + T.scratch, T.build_bytes, &st, stream, pl);
+      if (rc == MDP_OK) rc = build_with_plan(ctx, &q, env, &M, sc + T.scratch, T.build_bytes, &st, stream, plans[i]);
       if (rc == MDP_OK && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(ctx, e, "autotune record");
       if (rc == MDP_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(ctx, e, "autotune sync");
       float ms = 0.0f;
@@ -784,13 +787,16 @@ mdp_status mdp_autotune(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, 
         set_err(ctx, "autotune sample build failed: %s", mdp_status_str(st.status));
         rc = st.status;
       }
-      if (rc == MDP_OK && rep > 0) ms_best = std::min(ms_best, (double)ms);
+      if (rc == MDP_OK && round > 0) ms_best[i] = std::min(ms_best[i], (double)ms);
     }
+  }
+  int best = -1;
+  for (size_t i = 0; i < cands.size(); ++i) {
     out->row_lanes[i] = cands[i].row_lanes;
     out->rch[i] = cands[i].rch;
     out->pack16[i] = cands[i].pack16;
-    out->ms[i] = ms_best;
-    if (rc == MDP_OK && (best < 0 || ms_best < out->ms[best])) best = (int)i;
+    out->ms[i] = ms_best[i];
+    if (best < 0 || ms_best[i] < out->ms[best]) best = (int)i;
   }
   ctx->profiling = prof;
   (void)hipEventDestroy(e0);
