@@ -164,6 +164,7 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     hi[h] = (int)(min(max(rhi[h], eb), ee) - eb);
   }
   const uint32_t ns32 = (uint32_t)P.ns;
+  const uint32_t wbase32 = (uint32_t)wbase;
   double acc[2] = {0.0, 0.0};
   for (int base = 0; base < E; base += kViChunk) {
     const int ce = min(E - base, kViChunk);
@@ -172,7 +173,8 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
     __syncthreads();  // every wave's, and the previous round's reads are done
     // v_old of every entry's successor: one LDS read per entry, branch-free
     // (index 0 outside the window, sinks give 0), then global reads for the
-    // rare states outside the window
+    // rare states outside the window. Slots past the round's entries hold a
+    // valid entry; their products land past the rows' ranges, never summed.
     constexpr int kHalf = kViChunk / kBlock / 2;  // in two halves, to bound registers
 #pragma unroll
     for (int j0 = 0; j0 < kViChunk / kBlock; j0 += kHalf) {
@@ -180,11 +182,12 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
       uint32_t outside = 0;
 #pragma unroll
       for (int j = 0; j < kHalf; ++j) {
-        const int64_t w = (int64_t)cc[j0 + j] - wbase;  // sinks are never inside
-        const bool inw = w >= 0 && w < wn;
-        const double x = vwin[inw ? (int)w : 0];
+        // 32-bit: states and window bases are below 2^31; sinks are never inside
+        const uint32_t w = cc[j0 + j] - wbase32;
+        const bool inw = w < (uint32_t)wn;
+        const double x = vwin[inw ? w : 0u];
         vv[j] = inw ? x : 0.0;
-        outside |= (uint32_t)(!inw && cc[j0 + j] < ns32 && tid + kBlock * (j0 + j) < ce) << j;
+        outside |= (uint32_t)(!inw && cc[j0 + j] < ns32) << j;
       }
       if (outside) {
 #pragma unroll
@@ -192,10 +195,7 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
           if (outside >> j & 1) vv[j] = vin[cc[j0 + j]];
       }
 #pragma unroll
-      for (int j = 0; j < kHalf; ++j) {
-        const int k = tid + kBlock * (j0 + j);
-        if (k < ce) prod[k] = (double)nn[j0 + j] * vv[j];
-      }
+      for (int j = 0; j < kHalf; ++j) prod[tid + kBlock * (j0 + j)] = (double)nn[j0 + j] * vv[j];
     }
     __syncthreads();
     // ---- each row's products in ascending order (independent LDS reads)
@@ -630,6 +630,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     hi[h] = (int)(min(max(rhi[h], eb), ee) - eb);
   }
   const uint32_t ns32 = (uint32_t)P.ns;
+  const uint32_t wbase32 = (uint32_t)wbase;
   double acc[M][2];
 #pragma unroll
   for (int m = 0; m < M; ++m) acc[m][0] = acc[m][1] = 0.0;
@@ -642,6 +643,21 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     const int top = base + ce;
     if (base > 0 && !early) load_chunk(base);
     wait_vm();  // this chunk's entries, and (first round) this wave's copies
+    // once per round for all missions: each slot's window index (32-bit:
+    // states and window bases are below 2^31; sinks are never inside) in
+    // place of its column, and which slots are in the window or are states
+    // outside it (read from HBM; their columns are loaded again). Slots past
+    // the round's entries hold a valid entry; their products land past the
+    // rows' ranges and are never summed.
+    uint32_t in_w = 0, out_w = 0;
+#pragma unroll
+    for (int j = 0; j < CHM / kBlock; ++j) {
+      const uint32_t w = cc[j] - wbase32;
+      const bool inw = w < (uint32_t)wn;
+      in_w |= (uint32_t)inw << j;
+      out_w |= (uint32_t)(!inw && cc[j] < ns32) << j;
+      cc[j] = inw ? w : 0u;
+    }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!(live >> m & 1)) continue;
@@ -651,26 +667,20 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
 #pragma unroll
       for (int j0 = 0; j0 < CHM / kBlock; j0 += kHalf) {
         double vv[kHalf];
-        uint32_t outside = 0;
 #pragma unroll
         for (int j = 0; j < kHalf; ++j) {
-          const int64_t w = (int64_t)cc[j0 + j] - wbase;  // sinks are never inside
-          const bool inw = w >= 0 && w < wn;
-          const double x = vw[inw ? (int)w : 0];
-          vv[j] = inw ? x : 0.0;
-          outside |= (uint32_t)(!inw && cc[j0 + j] < ns32 && tid + kBlock * (j0 + j) < ce) << j;
+          const double x = vw[cc[j0 + j]];
+          vv[j] = (in_w >> (j0 + j) & 1) ? x : 0.0;
         }
-        if (outside) {
+        if ((out_w >> j0) & ((1u << kHalf) - 1u)) {
           const double *src = vin(m);
 #pragma unroll
           for (int j = 0; j < kHalf; ++j)
-            if (outside >> j & 1) vv[j] = src[cc[j0 + j]];
+            if (out_w >> (j0 + j) & 1)
+              vv[j] = src[colp[min(eb + base + tid + kBlock * (j0 + j), elast)]];
         }
 #pragma unroll
-        for (int j = 0; j < kHalf; ++j) {
-          const int k = tid + kBlock * (j0 + j);
-          if (k < ce) prod[k] = (double)nn[j0 + j] * vv[j];
-        }
+        for (int j = 0; j < kHalf; ++j) prod[tid + kBlock * (j0 + j)] = (double)nn[j0 + j] * vv[j];
       }
       if (m == M - 1 && top < E) load_chunk(top);  // (mission M - 1 is live: early)
       __syncthreads();
