@@ -643,21 +643,6 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
     const int top = base + ce;
     if (base > 0 && !early) load_chunk(base);
     wait_vm();  // this chunk's entries, and (first round) this wave's copies
-    // once per round for all missions: each slot's window index (32-bit:
-    // states and window bases are below 2^31; sinks are never inside) in
-    // place of its column, and which slots are in the window or are states
-    // outside it (read from HBM; their columns are loaded again). Slots past
-    // the round's entries hold a valid entry; their products land past the
-    // rows' ranges and are never summed.
-    uint32_t in_w = 0, out_w = 0;
-#pragma unroll
-    for (int j = 0; j < CHM / kBlock; ++j) {
-      const uint32_t w = cc[j] - wbase32;
-      const bool inw = w < (uint32_t)wn;
-      in_w |= (uint32_t)inw << j;
-      out_w |= (uint32_t)(!inw && cc[j] < ns32) << j;
-      cc[j] = inw ? w : 0u;
-    }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!(live >> m & 1)) continue;
@@ -667,18 +652,24 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
 #pragma unroll
       for (int j0 = 0; j0 < CHM / kBlock; j0 += kHalf) {
         double vv[kHalf];
+        uint32_t outside = 0;
 #pragma unroll
         for (int j = 0; j < kHalf; ++j) {
-          const double x = vw[cc[j0 + j]];
-          vv[j] = (in_w >> (j0 + j) & 1) ? x : 0.0;
+          // 32-bit: states and window bases are below 2^31; sinks are never inside
+          const uint32_t w = cc[j0 + j] - wbase32;
+          const bool inw = w < (uint32_t)wn;
+          const double x = vw[inw ? w : 0u];
+          vv[j] = inw ? x : 0.0;
+          outside |= (uint32_t)(!inw && cc[j0 + j] < ns32) << j;
         }
-        if ((out_w >> j0) & ((1u << kHalf) - 1u)) {
+        if (outside) {
           const double *src = vin(m);
 #pragma unroll
           for (int j = 0; j < kHalf; ++j)
-            if (out_w >> (j0 + j) & 1)
-              vv[j] = src[colp[min(eb + base + tid + kBlock * (j0 + j), elast)]];
+            if (outside >> j & 1) vv[j] = src[cc[j0 + j]];
         }
+        // slots past the round's entries hold a valid entry; their products
+        // land past the rows' ranges and are never summed
 #pragma unroll
         for (int j = 0; j < kHalf; ++j) prod[tid + kBlock * (j0 + j)] = (double)nn[j0 + j] * vv[j];
       }
