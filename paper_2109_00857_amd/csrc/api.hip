@@ -677,7 +677,7 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
 // The sample a launch shape is timed on: the problem's first layers, enough
 // of them for kTuneTiles cell tiles of the default shape (many waves of
 // resident workgroups, so the timing is the steady state, not the tail).
-static constexpr double kTuneTiles = 16384;
+static constexpr double kTuneTiles = 32768;
 static constexpr int kTuneRounds = 4;  // timed rounds over all candidates
 
 static const char *tune_sample(const mdp_problem *p, mdp_problem &q)
