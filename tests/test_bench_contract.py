@@ -1,0 +1,31 @@
+"""The benchmark's command-line contract, on the CPU (no GPU work is started)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_measured_traffic_matches_the_kernel_sources():
+    """Each recorded HBM traffic figure names the source it was measured on; a
+    stale figure is reported null rather than attributed to changed code."""
+    sys.path.insert(0, ROOT)
+    import hashlib
+
+    import bench
+
+    for kernel, m in bench.MEASURED_TRAFFIC.items():
+        with open(os.path.join(ROOT, m["src"]), "rb") as f:
+            current = hashlib.sha256(f.read()).hexdigest()[:16]
+        got = bench.measured_traffic(kernel)
+        if current == m["sha256"]:
+            assert got == m["read"] + m["write"] and got > 0, kernel
+        else:
+            assert got is None, kernel
