@@ -434,3 +434,181 @@ def test_subgrid_auto_uniform(ora):
     assert hx == 2 and hy == 1  # 1.5 + 1e-3 needs h = 2; 1.05 + 1e-3 needs h = 1
     w2 = W.uniform_flow(8, 8, 2, 1.0, 0.0, n_real=4, n_head=8, f_max=0.5, dt=1.0)
     assert ora.subgrid_auto(w2) == (2, 1)  # 1.501 > 1.5 forces h = 2; 0.501 < 1.5
+
+
+# ----------------------------------------------------------------------------------------
+# Near-edge flag: physical distance 1e-6 from a cell edge (cell units 1e-6/dx, 1e-6/dy)
+# ----------------------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_near_edge_flag_physical_units(ora, axis):
+    """Landings placed at chosen physical distances from a cell edge, on a grid with
+    dx != dy != 1: those within 1e-6 (physical units) of the edge are flagged, those
+    farther are not, and the row and model counts add up. An epsilon in cell units
+    (1e-6 instead of 1e-6/dx, 25x smaller here) or a looser threshold fails."""
+    nx, ny, nt = 25, 40, 2
+    dx, dy, dt = 1.0 / nx, 1.0 / ny, 0.05
+    # signed physical offsets of the landing from the edge at i + 1 (or j + 1)
+    offs = np.array([0.5e-6, -0.5e-6, 2e-6, -2e-6, 0.25e-6, -3e-6, 0.7e-6, 5e-6])
+    flagged = np.abs(offs) < 1e-6
+    nr = len(offs)
+    w = W.uniform_flow(nx, ny, nt, 0.0, 0.0, n_real=nr, n_head=2, f_max=0.0, dx=dx, dy=dy, dt=dt,
+                       mode_u=1.0 if axis == "x" else 0.0, mode_v=0.0 if axis == "x" else 1.0,
+                       start=(0, 0), target=(nx - 1, ny - 1), sub_h=2)
+    d = dx if axis == "x" else dy
+    # speed whose one-step displacement from the cell centre is half a cell plus the offset
+    w.mu[:, 0, :] = ((0.5 * d + offs) / dt).astype(np.float32)
+    i0, j0 = 7, 11
+    c = j0 * nx + i0
+    for r in range(nr):
+        # independent fp64 check that the stored coefficient keeps the intended distance
+        x = ((i0 if axis == "x" else j0) + 0.5) * d + float(w.mu[0, 0, r]) * dt
+        dist = abs(x - round(x / d) * d)
+        assert abs(dist - abs(offs[r])) < 0.05e-6, (r, dist, offs[r])
+        for a in range(2):
+            ip, jp, ne = ora.landing(w, 0, c, r, a)
+            assert ne == bool(flagged[r]), (axis, r, offs[r])
+            exp = (i0 + (1 if offs[r] > 0 else 0), j0) if axis == "x" else (i0, j0 + (1 if offs[r] > 0 else 0))
+            assert (ip, jp) == exp, (axis, r, ip, jp, exp)
+    _, _, _, _, _, nn = ora.row(w, 0, c, 0)
+    assert nn == int(flagged.sum())
+    m = ora.build_model(w)
+    src = np.arange(w.n_states) % (nx * ny)
+    n_src = int((src != (ny - 1) * nx + (nx - 1)).sum())  # every source but the target
+    assert m["n_near_edge"] == n_src * 2 * int(flagged.sum())
+
+
+# ----------------------------------------------------------------------------------------
+# Several speeds: action order a = j*N_h + h, speed F_j = F_max (j+1)/N_F
+# ----------------------------------------------------------------------------------------
+def test_two_speeds_zero_coefficients_one_hot(ora):
+    """With two speeds and zero coefficients every row is one-hot at the cell of
+    x + (vbar + F_j (cos th_h, sin th_h)) dt evaluated in fp64 physical units,
+    for a = j*N_h + h; the action tables hold the two speeds."""
+    w = W.uniform_flow(9, 8, 3, 0.27, -0.13, n_real=4, n_head=6, f_max=1.6, dx=1.0, dy=1.0, dt=1.0,
+                       start=(0, 0), target=(8, 7), sub_h=3, n_speed=2, mission_mask=3)
+    m = ora.build_model(w)
+    p = w.problem
+    nx, ny, nt = p["nx"], p["ny"], p["nt"]
+    na, nc = w.n_actions, nx * ny
+    assert na == 12
+    hx, hy, sp = ora.action_tables(w)
+    for a in range(na):
+        jf, h = divmod(a, 6)
+        F = 1.6 * (jf + 1) / 2
+        assert sp[a] == F
+        assert abs(hx[a] - F * math.cos(2 * math.pi * h / 6)) < 1e-6
+        assert abs(hy[a] - F * math.sin(2 * math.pi * h / 6)) < 1e-6
+    checked = 0
+    for t in range(nt):
+        for a in range(na):
+            ip, jp = _fp64_landings(w, t, a)
+            for c in range(nc):
+                row = (t * nc + c) * na + a
+                lo, hi = m["row_ptr"][row], m["row_ptr"][row + 1]
+                assert hi - lo == 1 and m["cnt"][lo] == p["n_real"]
+                if (c % nx, c // nx) == (p["target_i"], p["target_j"]) or m["row_near"][row]:
+                    continue
+                exp = _classify_counts(w, t, c, ip[c][:1], jp[c][:1])
+                assert list(exp) == [m["col"][lo]], (t, c, a)
+                checked += 1
+    assert checked > 0.9 * nt * nc * na
+    # the fast speed of a heading reaches farther than the slow one somewhere
+    i_slow, _ = _fp64_landings(w, 0, 0)
+    i_fast, _ = _fp64_landings(w, 0, 6)
+    assert (i_fast[:, 0] > i_slow[:, 0]).any()
+
+
+def test_two_speed_energy_reward_identity(ora):
+    """Energy mission with two speeds: R = -c_f F_j^2 dt (p_state + p_target)
+    + r_term p_target + r_outbound p_dead, with F_j the action's own speed; the
+    time mission does not depend on the speed."""
+    w = W.config2(nx=18, ny=16, nt=3, n_real=300, K=4, n_head=5)
+    w.problem["n_speed"] = 2
+    w.problem["c_f"] = 0.75
+    m = ora.build_model(w)
+    p = w.problem
+    ns, na, nr = w.n_states, w.n_actions, p["n_real"]
+    nc = p["nx"] * p["ny"]
+    dt = p["dt"]
+    seen = set()
+    for row in range(w.n_rows):
+        s, a = divmod(row, na)
+        t, c = divmod(s, nc)
+        if (c % p["nx"], c // p["nx"]) == (p["target_i"], p["target_j"]) or w.mask[t].reshape(-1)[c]:
+            continue
+        F = p["f_max"] * (a // p["n_head"] + 1) / p["n_speed"]
+        pn, pt, pd = _probs(m, row, ns, nr)
+        rt = -dt * pn + (p["r_term"] - dt) * pt + p["r_outbound"] * pd
+        re = -p["c_f"] * F * F * dt * (pn + pt) + p["r_term"] * pt + p["r_outbound"] * pd
+        assert abs(m["R"][0, row] - rt) <= 1e-12 * (1 + abs(rt))
+        assert abs(m["R"][1, row] - re) <= 1e-12 * (1 + abs(re)), (row, a, F)
+        if pd == 0 and pt == 0:
+            seen.add(a // p["n_head"])
+    assert seen == {0, 1}  # both speeds checked on rows without sinks
+
+
+# ----------------------------------------------------------------------------------------
+# Tolerance scales: A = E|r| per row and w = value of |r| under the oracle's policy
+# ----------------------------------------------------------------------------------------
+def test_expected_abs_reward_closed_form(ora):
+    """A, the per-row expected |reward| that scales the reward tolerance, in closed
+    form: time A = dt p_state + |r_term - dt| p_target + |r_out| p_dead, energy the
+    same with c_f F^2 dt; a net-energy mission over a constant field G with
+    c_r G > c_f F^2 has positive step rewards: A = (c_r G - c_f F^2) dt (p_state +
+    p_target) + r_term p_target + |r_out| p_dead."""
+    G = 0.8
+    w = W.config2(nx=16, ny=15, nt=3, n_real=250, K=4, n_head=6)
+    w.gbar = np.full((4, 15, 16), G, np.float32)
+    w.problem["n_speed"] = 2
+    w.problem["r_term"] = 0.02  # below dt: the target step reward is negative in the time mission
+    m = ora.build_model(w)
+    p = w.problem
+    ns, na, nr, nc = w.n_states, w.n_actions, p["n_real"], p["nx"] * p["ny"]
+    dt, rt_, ro = p["dt"], p["r_term"], p["r_outbound"]
+    assert rt_ < dt
+    Gf = float(np.float32(G))
+    for row in range(w.n_rows):
+        s, a = divmod(row, na)
+        t, c = divmod(s, nc)
+        i, j = c % p["nx"], c // p["nx"]
+        if (i, j) == (p["target_i"], p["target_j"]):
+            assert (m["A"][:, row] == 0).all()
+            continue
+        if w.mask[t, j, i]:
+            assert (m["A"][:, row] == abs(ro)).all()
+            continue
+        F = p["f_max"] * (a // p["n_head"] + 1) / p["n_speed"]
+        e = p["c_f"] * F * F * dt
+        pn, pt, pd = _probs(m, row, ns, nr)
+        a_time = dt * pn + abs(rt_ - dt) * pt + abs(ro) * pd
+        a_en = e * pn + abs(rt_ - e) * pt + abs(ro) * pd
+        g = (p["c_r"] * Gf - p["c_f"] * F * F) * dt
+        assert g > 0
+        a_net = g * (pn + pt) + rt_ * pt + abs(ro) * pd
+        for k, ex in enumerate((a_time, a_en, a_net)):
+            assert abs(m["A"][k, row] - ex) <= 1e-12 * (1 + ex), (row, k, m["A"][k, row], ex)
+
+
+def test_value_scale_of_abs_rewards(ora):
+    """w, the value of |rewards| under the oracle's policy that scales the value
+    tolerance: with every reward non-positive it is exactly -v; in general it is
+    at least |v| and obeys w(s) = A(s, pi(s)) + sum P w(s') for the policy's action."""
+    w = W.config1(nt=5, n_real=200, sub_h=4)
+    w.problem["r_term"] = 0.0  # arrival then costs dt like any other step: all rewards <= 0
+    m = ora.build_model(w)
+    v, pi, wa = ora.backward(w, m, 0)
+    assert (m["R"][0] <= 0).all()
+    np.testing.assert_array_equal(wa, -v)
+    w2 = W.config2(nx=14, ny=13, nt=4, n_real=300, K=4, n_head=8)  # r_term = 100: mixed signs
+    m2 = ora.build_model(w2)
+    ns, na = w2.n_states, w2.n_actions
+    for mission in (0, 2):
+        v, pi, wa = ora.backward(w2, m2, mission)
+        assert (wa >= np.abs(v) - 1e-9 * (1 + np.abs(v))).all()
+        assert (wa > np.abs(v) + 1e-6).any()  # sign cancellation happens somewhere
+        rp, col, cnt = m2["row_ptr"], m2["col"], m2["cnt"]
+        for s in range(0, ns, 7):
+            row = s * na + pi[s]
+            ex = m2["A"][mission, row] + sum(cnt[k] / w2.problem["n_real"] * wa[col[k]]
+                                             for k in range(rp[row], rp[row + 1]) if col[k] < ns)
+            assert abs(wa[s] - ex) <= 1e-9 * (1 + abs(ex))
