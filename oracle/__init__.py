@@ -79,6 +79,7 @@ def load():
         lib.ora_jacobi.argtypes = [P, vp, vp, vp, vp, C.c_double, C.c_int32, vp, vp]
         lib.ora_jacobi.restype = C.c_int32
         lib.ora_q.argtypes = [P, vp, vp, vp, vp, vp, vp, C.c_int64, vp]
+        lib.ora_rollout.argtypes = [P, E, vp, vp, vp, vp, vp, vp, vp]
         lib.ora_max_speed.argtypes = [P, E, vp, vp]
         lib.ora_subgrid_auto.argtypes = [P, E, vp, vp]
         _lib = lib
@@ -217,3 +218,52 @@ def subgrid_auto(w):
     hx, hy = C.c_int32(), C.c_int32()
     lib.ora_subgrid_auto(C.byref(b.p), C.byref(b.e), C.byref(hx), C.byref(hy))
     return hx.value, hy.value
+
+
+ROLL_ARRIVED, ROLL_OUTBOUND, ROLL_OBSTACLE, ROLL_HORIZON = 0, 1, 2, 3
+
+
+def rollout(w, pi) -> dict:
+    """Policy pi [n_states] followed from the start in every realization: per
+    realization trajectory [n_real][nt+1], outcome, steps, returns [n_real][3],
+    energy expended and speed sum; plus the ensemble statistics."""
+    lib = load()
+    b = _Bound(w)
+    p = w.problem
+    nr, nt = p["n_real"], p["nt"]
+    pi = np.ascontiguousarray(pi, np.int32)
+    traj = np.zeros((nr, nt + 1), np.int32)
+    outcome = np.zeros(nr, np.int32)
+    steps = np.zeros(nr, np.int32)
+    ret = np.zeros((nr, 3))
+    energy = np.zeros(nr)
+    fsum = np.zeros(nr)
+    lib.ora_rollout(C.byref(b.p), C.byref(b.e), _ptr(pi), _ptr(traj), _ptr(outcome), _ptr(steps), _ptr(ret),
+                    _ptr(energy), _ptr(fsum))
+    return dict(traj=traj, outcome=outcome, steps=steps, ret=ret, energy=energy, fsum=fsum,
+                **rollout_summary(w, outcome, steps, ret, energy, fsum))
+
+
+def rollout_summary(w, outcome, steps, ret, energy, fsum) -> dict:
+    """Ensemble statistics of rollouts: P(reach), and over the arrived paths the
+    mean travel time, energy expended, net energy consumed (energy expended
+    minus energy harvested) and speed; the mean return of each mission over all
+    paths. Plain sums in realization order."""
+    p = w.problem
+    arr = outcome == ROLL_ARRIVED
+    n_arr = int(arr.sum())
+    out = dict(n_real=len(outcome), n_arrived=n_arr, n_outbound=int((outcome == ROLL_OUTBOUND).sum()),
+               n_obstacle=int((outcome == ROLL_OBSTACLE).sum()), n_horizon=int((outcome == ROLL_HORIZON).sum()),
+               p_reach=n_arr / len(outcome))
+    if n_arr:
+        sa = steps[arr].astype(np.float64)
+        out["mean_time_arrived"] = float(sum(sa) * p["dt"] / n_arr)
+        out["mean_energy_arrived"] = float(sum(energy[arr]) / n_arr)
+        # an arrived path's net-energy return is r_term minus its net consumption
+        out["mean_net_energy_arrived"] = float(sum(p["r_term"] - ret[arr, 2]) / n_arr)
+        out["mean_speed_arrived"] = float(sum(fsum[arr]) / sum(sa)) if sa.sum() > 0 else 0.0
+    else:
+        out.update(mean_time_arrived=0.0, mean_energy_arrived=0.0, mean_net_energy_arrived=0.0,
+                   mean_speed_arrived=0.0)
+    out["mean_return"] = [float(sum(ret[:, m]) / len(outcome)) for m in range(3)]
+    return out

@@ -322,6 +322,92 @@ void ora_q(const ora_problem *p, const int64_t *row_ptr, const int32_t *col,
       q[k * na + a] = q_value(p, row_ptr, col, cnt, R, v, s_idx[k] * na + a);
 }
 
+/* Rollout of a policy through the ensemble (Sec. IV applies each optimal
+ * policy to every realization of the flow and reports the resulting
+ * trajectories, expected travel time and energy). In realization r the agent
+ * at layer t in cell c takes action pi(t, c) and lands where the kinematic
+ * step of that realization puts it (the same landing as a sample of the
+ * transition model); the landing is classified with the rules of ora_row, and
+ * its one-step reward is added to the realized return of each mission:
+ *   outside the domain or on an obstacle at t+1: r_outbound, the path ends;
+ *   the target: base + r_term, the path ends (arrived);
+ *   beyond the horizon (t+1 = nt): r_outbound, the path ends;
+ *   otherwise base, and the path continues from (t+1, c').
+ * A path that starts on the target has arrived after 0 steps with return 0; one
+ * that starts in an obstacle ends at once with return r_outbound (the fixed
+ * rows of those states). */
+void ora_rollout(const ora_problem *p, const ora_env *e, const int32_t *pi, int32_t *traj,
+                 int32_t *outcome, int32_t *steps, double *ret, double *energy, double *fsum)
+{
+  const int nx = p->nx, ny = p->ny, nt = p->nt;
+  const int nc = nx * ny;
+  double speed[ORA_MAX_ACTIONS];
+  float hx[ORA_MAX_ACTIONS], hy[ORA_MAX_ACTIONS];
+  ora_action_tables(p, hx, hy, speed);
+  for (int r = 0; r < p->n_real; ++r) {
+    int32_t *tr = traj ? traj + (size_t)r * (nt + 1) : NULL;
+    double R[3] = {0.0, 0.0, 0.0}, E = 0.0, Fs = 0.0;
+    int i = p->start_i, j = p->start_j, n = 0, out = ORA_ROLL_HORIZON;
+    int t = 0;
+    if (tr)
+      for (int k = 0; k <= nt; ++k) tr[k] = -1;
+    if (tr) tr[0] = j * nx + i;
+    for (t = 0; t < nt; ++t) {
+      const int c = j * nx + i;
+      if (i == p->target_i && j == p->target_j) {
+        out = ORA_ROLL_ARRIVED;
+        break;
+      }
+      if (e->mask && e->mask[(size_t)t * nc + c]) {
+        for (int m = 0; m < 3; ++m) R[m] += p->r_outbound;
+        out = ORA_ROLL_OBSTACLE;
+        break;
+      }
+      const int a = pi[(size_t)t * nc + c];
+      int32_t ip, jp, ne;
+      landing(p, e, hx, hy, t, c, r, a, &ip, &jp, &ne);
+      const double F = speed[a], e_a = p->c_f * F * F;
+      ++n;
+      E += e_a * p->dt;
+      Fs += F;
+      if (ip < 0 || ip >= nx || jp < 0 || jp >= ny) {
+        for (int m = 0; m < 3; ++m) R[m] += p->r_outbound;
+        out = ORA_ROLL_OUTBOUND;
+        break;
+      }
+      const int cp = jp * nx + ip;
+      if (e->mask && e->mask[(size_t)(t + 1) * nc + cp]) {
+        for (int m = 0; m < 3; ++m) R[m] += p->r_outbound;
+        out = ORA_ROLL_OBSTACLE;
+        break;
+      }
+      const double g_s = e->gbar ? (double)e->gbar[(size_t)t * nc + c] : 0.0;
+      const double g_sp = e->gbar ? (double)e->gbar[(size_t)(t + 1) * nc + cp] : 0.0;
+      const double base[3] = {-p->dt, -e_a * p->dt, (-e_a + 0.5 * p->c_r * g_s + 0.5 * p->c_r * g_sp) * p->dt};
+      if (ip == p->target_i && jp == p->target_j) {
+        for (int m = 0; m < 3; ++m) R[m] += base[m] + p->r_term;
+        if (tr) tr[t + 1] = cp;
+        out = ORA_ROLL_ARRIVED;
+        break;
+      }
+      if (t + 1 == nt) {
+        for (int m = 0; m < 3; ++m) R[m] += p->r_outbound;
+        out = ORA_ROLL_HORIZON;
+        break;
+      }
+      for (int m = 0; m < 3; ++m) R[m] += base[m];
+      i = ip;
+      j = jp;
+      if (tr) tr[t + 1] = cp;
+    }
+    outcome[r] = out;
+    steps[r] = n;
+    for (int m = 0; m < 3; ++m) ret[(size_t)r * 3 + m] = R[m];
+    energy[r] = E;
+    fsum[r] = Fs;
+  }
+}
+
 void ora_max_speed(const ora_problem *p, const ora_env *e, double *umax, double *vmax)
 {
   const int nc = p->nx * p->ny;

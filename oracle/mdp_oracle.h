@@ -83,6 +83,22 @@ void ora_q(const ora_problem *p, const int64_t *row_ptr, const int32_t *col,
            const int32_t *cnt, const double *R, const double *v,
            const int64_t *s_idx, int64_t n, double *q);
 
+/* Outcome of one rollout (ora_rollout). */
+#define ORA_ROLL_ARRIVED 0   /* reached the target                              */
+#define ORA_ROLL_OUTBOUND 1  /* a landing left the domain                       */
+#define ORA_ROLL_OBSTACLE 2  /* landed on (or started in) an obstacle           */
+#define ORA_ROLL_HORIZON 3   /* still travelling after the last decision layer  */
+
+/* Follow the policy pi [nt*nx*ny] from the start cell at t = 0 in every flow
+ * realization r (the realization's coefficients mu[t][.][r] at each layer).
+ * Per realization: traj [n_real][nt+1] the cell index at each layer (-1 once
+ * the path has ended; the target cell at the arrival layer), outcome, the
+ * decision steps taken, the realized return of each mission ret [n_real][3]
+ * (the one-step rewards of the landings along the path), the energy expended
+ * (sum of c_f F^2 dt) and the sum of the speeds used. traj may be NULL. */
+void ora_rollout(const ora_problem *p, const ora_env *e, const int32_t *pi, int32_t *traj,
+                 int32_t *outcome, int32_t *steps, double *ret, double *energy, double *fsum);
+
 /* Largest |u| and |v| over all synthesised velocities (t, c, r) in FP32. */
 void ora_max_speed(const ora_problem *p, const ora_env *e, double *umax, double *vmax);
 
