@@ -80,6 +80,8 @@ def load():
         lib.ora_jacobi.restype = C.c_int32
         lib.ora_q.argtypes = [P, vp, vp, vp, vp, vp, vp, C.c_int64, vp]
         lib.ora_rollout.argtypes = [P, E, vp, vp, vp, vp, vp, vp, vp]
+        lib.ora_segment_meets_cell.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int]
+        lib.ora_segment_meets_cell.restype = C.c_int
         lib.ora_max_speed.argtypes = [P, E, vp, vp]
         lib.ora_subgrid_auto.argtypes = [P, E, vp, vp]
         _lib = lib
@@ -267,3 +269,10 @@ def rollout_summary(w, outcome, steps, ret, energy, fsum) -> dict:
                    mean_speed_arrived=0.0)
     out["mean_return"] = [float(sum(ret[:, m]) / len(outcome)) for m in range(3)]
     return out
+
+
+FLAG_SWEPT_PATH = 2
+
+
+def segment_meets_cell(x0, y0, x1, y1, a, b) -> bool:
+    return bool(load().ora_segment_meets_cell(x0, y0, x1, y1, a, b))

@@ -65,8 +65,9 @@ static void ora_velocity(const ora_problem *p, const ora_env *e, int t, int c, i
  *   px = fma(u, dt/dx, i + 1/2);  X = px + Hx[a];  i' = floor(X)   (same in y)
  * A sample is near an edge when X or Y lies within 1e-6 (physical units) of
  * an integer. */
-static void landing(const ora_problem *p, const ora_env *e, const float *hx, const float *hy,
-                    int t, int c, int r, int a, int32_t *ip, int32_t *jp, int32_t *near_edge)
+static void landing_xy(const ora_problem *p, const ora_env *e, const float *hx, const float *hy,
+                       int t, int c, int r, int a, int32_t *ip, int32_t *jp, int32_t *near_edge,
+                       float *Xo, float *Yo)
 {
   const int i = c % p->nx, j = c / p->nx;
   const float lam_x = (float)(p->dt / p->dx), lam_y = (float)(p->dt / p->dy);
@@ -80,6 +81,14 @@ static void landing(const ora_problem *p, const ora_env *e, const float *hx, con
   *ip = (int32_t)floorf(X);
   *jp = (int32_t)floorf(Y);
   *near_edge = (fabsf(X - rintf(X)) < eps_x) || (fabsf(Y - rintf(Y)) < eps_y);
+  if (Xo) *Xo = X;
+  if (Yo) *Yo = Y;
+}
+
+static void landing(const ora_problem *p, const ora_env *e, const float *hx, const float *hy,
+                    int t, int c, int r, int a, int32_t *ip, int32_t *jp, int32_t *near_edge)
+{
+  landing_xy(p, e, hx, hy, t, c, r, a, ip, jp, near_edge, NULL, NULL);
 }
 
 void ora_landing(const ora_problem *p, const ora_env *e, int t, int c, int r, int a,
@@ -88,6 +97,48 @@ void ora_landing(const ora_problem *p, const ora_env *e, int t, int c, int r, in
   float hx[ORA_MAX_ACTIONS], hy[ORA_MAX_ACTIONS];
   ora_action_tables(p, hx, hy, NULL);
   landing(p, e, hx, hy, t, c, r, a, ip, jp, near_edge);
+}
+
+/* Separating-axis test of a closed segment against an open unit square: they
+ * meet iff their projections overlap on the x axis, on the y axis and on the
+ * segment's normal. With P0 = (i + 1/2, j + 1/2) and P1 = (X, Y) from FP32
+ * landings (coordinates below 2^24 in magnitude with 24-bit mantissas), every
+ * difference and product below is exact in double precision, so the test is
+ * exact and its outcome does not depend on the evaluation order. */
+int ora_segment_meets_cell(double x0, double y0, double x1, double y1, int a, int b)
+{
+  const double lx = x0 < x1 ? x0 : x1, hx = x0 < x1 ? x1 : x0;
+  const double ly = y0 < y1 ? y0 : y1, hy = y0 < y1 ? y1 : y0;
+  if (!(lx < (double)a + 1.0 && hx > (double)a)) return 0;
+  if (!(ly < (double)b + 1.0 && hy > (double)b)) return 0;
+  const double dx = x1 - x0, dy = y1 - y0;
+  double fmin = 0.0, fmax = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const double cx = (double)(a + (k & 1)), cy = (double)(b + (k >> 1));
+    const double f = dx * (cy - y0) - dy * (cx - x0); /* side of the corner w.r.t. the line */
+    if (k == 0 || f < fmin) fmin = f;
+    if (k == 0 || f > fmax) fmax = f;
+  }
+  return fmin < 0.0 && fmax > 0.0;
+}
+
+/* Swept-path reading of the obstacle test of Alg. 2: the straight path of the
+ * step from the source cell centre to the landing point crosses an obstacle
+ * cell at t+1 other than the source cell. */
+static int swept_blocked(const ora_problem *p, const ora_env *e, int t, int i, int j, float X, float Y)
+{
+  if (!(p->flags & ORA_FLAG_SWEPT_PATH) || !e->mask) return 0;
+  const int nx = p->nx, ny = p->ny;
+  const double x0 = (double)i + 0.5, y0 = (double)j + 0.5, x1 = (double)X, y1 = (double)Y;
+  const int a0 = (int)floor(x0 < x1 ? x0 : x1), a1 = (int)floor(x0 < x1 ? x1 : x0);
+  const int b0 = (int)floor(y0 < y1 ? y0 : y1), b1 = (int)floor(y0 < y1 ? y1 : y0);
+  for (int b = b0; b <= b1; ++b)
+    for (int a = a0; a <= a1; ++a) {
+      if ((a == i && b == j) || a < 0 || a >= nx || b < 0 || b >= ny) continue;
+      if (!e->mask[(size_t)(t + 1) * nx * ny + (size_t)b * nx + a]) continue;
+      if (ora_segment_meets_cell(x0, y0, x1, y1, a, b)) return 1;
+    }
+  return 0;
 }
 
 static int cmp_i32(const void *x, const void *y)
@@ -147,13 +198,14 @@ int32_t ora_row(const ora_problem *p, const ora_env *e, int t, int c, int a,
   double sum[3] = {0, 0, 0}, asum[3] = {0, 0, 0};
   for (int r = 0; r < nr; ++r) {
     int32_t ip, jp, ne;
-    landing(p, e, hx, hy, t, c, r, a, &ip, &jp, &ne);
+    float X, Y;
+    landing_xy(p, e, hx, hy, t, c, r, a, &ip, &jp, &ne, &X, &Y);
     if (ne) ++*n_near_edge;
     if (abs(ip - i) > p->sub_hx || abs(jp - j) > p->sub_hy) ++*n_escape;
 
     int32_t col;
     double rr[3];
-    if (ip < 0 || ip >= nx || jp < 0 || jp >= ny) {
+    if (ip < 0 || ip >= nx || jp < 0 || jp >= ny || swept_blocked(p, e, t, i, j, X, Y)) {
       col = DEAD;
       rr[0] = rr[1] = rr[2] = p->r_outbound;
     } else {
@@ -365,7 +417,8 @@ void ora_rollout(const ora_problem *p, const ora_env *e, const int32_t *pi, int3
       }
       const int a = pi[(size_t)t * nc + c];
       int32_t ip, jp, ne;
-      landing(p, e, hx, hy, t, c, r, a, &ip, &jp, &ne);
+      float X, Y;
+      landing_xy(p, e, hx, hy, t, c, r, a, &ip, &jp, &ne, &X, &Y);
       const double F = speed[a], e_a = p->c_f * F * F;
       ++n;
       E += e_a * p->dt;
@@ -376,7 +429,7 @@ void ora_rollout(const ora_problem *p, const ora_env *e, const int32_t *pi, int3
         break;
       }
       const int cp = jp * nx + ip;
-      if (e->mask && e->mask[(size_t)(t + 1) * nc + cp]) {
+      if ((e->mask && e->mask[(size_t)(t + 1) * nc + cp]) || swept_blocked(p, e, t, i, j, X, Y)) {
         for (int m = 0; m < 3; ++m) R[m] += p->r_outbound;
         out = ORA_ROLL_OBSTACLE;
         break;

@@ -44,6 +44,16 @@ typedef struct ora_env {
   const uint8_t *mask;         /* [nt+1][ny][nx] or NULL                      */
 } ora_env;
 
+/* Problem flags the oracle reads (bit values of the planner's problem flags). */
+#define ORA_FLAG_NEAR_EDGE 1u
+#define ORA_FLAG_SWEPT_PATH 2u /* a landing whose straight path from the cell centre
+                                  enters an obstacle cell at t+1 is DEAD        */
+
+/* Does the segment from (x0, y0) to (x1, y1) (cell units) meet the interior of
+ * cell (a, b), the open square (a, a+1) x (b, b+1)? Exact for the coordinates
+ * the planner produces (see the definition). */
+int ora_segment_meets_cell(double x0, double y0, double x1, double y1, int a, int b);
+
 /* Action tables: displacement of heading/speed a in cell units and its speed. */
 void ora_action_tables(const ora_problem *p, float *hx, float *hy, double *speed);
 

@@ -612,3 +612,25 @@ def test_value_scale_of_abs_rewards(ora):
             ex = m2["A"][mission, row] + sum(cnt[k] / w2.problem["n_real"] * wa[col[k]]
                                              for k in range(rp[row], rp[row + 1]) if col[k] < ns)
             assert abs(wa[s] - ex) <= 1e-9 * (1 + abs(ex))
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_two_speed_corridor_trade_off(ora, case):
+    """Hand-derived two-speed corridor: the energy mission takes the slow speed
+    when the horizon allows it and the fast one when it must; the time mission
+    takes the fast one. Values match the hand derivation and the exhaustive
+    search over deterministic Markov policies."""
+    from oracle import bruteforce
+
+    g = _golden("two_speed_corridor.json")
+    s, c = g["setup"], g["cases"][case]
+    w = W.uniform_flow(s["nx"], s["ny"], c["nt"], s["u0"], s["v0"], n_real=8, n_head=s["n_head"], f_max=s["f_max"],
+                       dx=s["dx"], dy=s["dy"], dt=s["dt"], start=tuple(s["start"]), target=tuple(s["target"]),
+                       sub_h=2, n_speed=s["n_speed"], mission_mask=3)
+    m = ora.build_model(w)
+    assert m["n_near_edge"] == 0 and m["n_escape"] == 0
+    v, pi, _ = ora.backward(w, m, c["mission"])
+    s0 = s["start"][1] * s["nx"] + s["start"][0]
+    assert abs(v[s0] - c["v_start"]) < 1e-12 and pi[s0] == c["pi_start"], (v[s0], pi[s0])
+    best, npol = bruteforce.best_policy_return(m, w.problem, c["mission"])
+    assert abs(best - v[s0]) < 1e-12 and npol >= 8
