@@ -1,11 +1,17 @@
 """Benchmark of the end-to-end planning step on one MI355X.
 
-One step = mdp_build of the paper-shaped instance (100x100 cells, 120 layers,
-5000 flow realizations, 16 headings, all three missions from one histogram
-pass) + value iteration to convergence for each mission (the three missions in
-one mdp_value_iterate_missions solve, which reads the shared transition entries
-once per sweep) + mdp_policy for each mission. Inputs are resident in HBM before
-the timed region.
+One step = mdp_build of one instance (every (layer, cell, action) row from all
+flow realizations, all requested missions from one histogram pass) + value
+iteration to convergence (the instance's missions in one
+mdp_value_iterate_missions solve) + mdp_policy per mission. Inputs are resident
+in HBM before the timed region.
+
+The headline step is the large instance: 200 x 200 cells, 200 layers, 16 modes,
+10000 AR(1) realizations, 32 headings, 7 x 7 sub-grid, net-energy mission (the
+paper's 200 x 200 x 200 shape). The paper-shaped instance (100 x 100 x 120,
+5000 realizations, 16 headings, three missions) is timed the same way and
+reported under "paper_shaped"; the 64-instance batch and the served trace are
+reported beside.
 
 Prints one JSON line: whole-step throughput in build samples per second, the
 build and value-iteration rates on their own, a roofline entry per hot kernel
@@ -27,28 +33,50 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # one VALU lane-op per lane per clock: 3.
 FP32_VECTOR = 157.3e12                 # packed-FMA FP32 vector peak (FLOP/s)
 HBM_BW = 8.0e12                        # bytes/s
 
-
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this workload
-# (profiles/paper_shaped_step_hbm_counters.md; FETCH_SIZE scaled x2.000 and
-# WRITE_SIZE x1.000 by a plain 1 GiB copy). They hold for the kernel source
-# whose sha256 prefix is given; after any change the traffic is reported null.
-MEASURED_TRAFFIC = {
-    "k_vi_sweep_missions<3>": dict(read=416382836, write=14990361, src="paper_2109_00857_amd/csrc/vi.hip",
-                                   sha256="1731d5bb665d1631"),
-    "k_build": dict(read=443800111, write=882340240, src="paper_2109_00857_amd/csrc/build.hip",
-                    sha256="e21e074de0a0dd60"),
-}
+# Counters per launch from rocprofv3 on this benchmark (profiles/*.md), each for
+# the kernel source whose sha256 prefix is given; after any change to that
+# source the figure is reported null. FETCH_SIZE / WRITE_SIZE are already
+# scaled to bytes by the plain-copy calibration (FETCH x2.000, WRITE x1.000);
+# valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
+MEASURED = {}
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch (read + write) measured for this kernel source, or None."""
+def _src_sha(src: str) -> str:
     import hashlib
 
-    m = MEASURED_TRAFFIC[kernel]
-    with open(os.path.join(ROOT, m["src"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != m["sha256"]:
-            return None
-    return m["read"] + m["write"]
+    with open(os.path.join(ROOT, src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured(kernel: str, workload: str, field: str):
+    """A counter figure per launch of this kernel on this workload, measured on the
+    current kernel source, or None."""
+    m = MEASURED.get((kernel, workload))
+    if m is None or m.get(field) is None or _src_sha(m["src"]) != m["sha256"]:
+        return None
+    return m[field]
+
+
+def measured_traffic(kernel: str, workload: str):
+    r, w = measured(kernel, workload, "read"), measured(kernel, workload, "write")
+    return None if r is None or w is None else r + w
+
+
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=usable)
 
 
 def cpu_baseline(w, seconds: float = 12.0):
@@ -71,10 +99,12 @@ def cpu_baseline(w, seconds: float = 12.0):
         n_rows += 1
         n_samples += nr
     dt = time.perf_counter() - t0
+    cpu = host_cpu()
     return dict(value=n_samples / dt, unit="samples/s", cores=1, kind="oracle",
-                sample=f"{n_rows} random (t, cell, action) rows of the same workload, "
+                sample=f"{n_rows} random (t, cell, action) rows of the {w.name} workload, "
                        f"{n_samples} realization landings, full-domain binning and fp64 rewards, "
-                       f"{dt:.1f} s on one host core")
+                       f"{dt:.1f} s on one host core",
+                host_cpu=cpu["model"], host_logical_cpus=cpu["logical_cpus"], host_usable_cpus=cpu["usable_cpus"])
 
 
 def _ev_ms(stream, fn, reps: int) -> float:
@@ -89,6 +119,226 @@ def _ev_ms(stream, fn, reps: int) -> float:
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def skipped_fraction(w) -> float:
+    """Share of the nominal samples whose source cell is the target or an obstacle
+    (their rows are fixed single entries; no landing is computed for them)."""
+    import numpy as np
+
+    p = w.problem
+    nc = p["nx"] * p["ny"]
+    skip = np.zeros((p["nt"], nc), bool)
+    skip[:, p["target_j"] * p["nx"] + p["target_i"]] = True
+    if w.mask is not None:
+        skip |= w.mask[:-1].reshape(p["nt"], nc).astype(bool)
+    return float(skip.mean())
+
+
+def rollout_leg(pl, w, p, env, pis, missions, reps: int = 3) -> dict:
+    """Each mission's policy rolled out in every realization (mdp_rollout, the
+    paper's Sec. IV use of the policies): ensemble statistics and the time of
+    one rollout (HIP events, inputs resident)."""
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    nr, nt = p["n_real"], p["nt"]
+    scratch = torch.empty(mdp.mdp_rollout_query(p), dtype=torch.uint8, device=pl.device)
+    traj = torch.empty((nt + 1, nr), dtype=torch.int32, device=pl.device)
+    st = mdp.stats_buffer(mdp.MdpRolloutStats)
+    s = torch.cuda.current_stream()
+    out = {}
+    for m, pi in zip(missions, pis):
+        ms = _ev_ms(s, lambda: mdp.mdp_rollout(pl.ctx, p, env, pi, traj, None, scratch, st, s), reps)
+        torch.cuda.synchronize()
+        d = mdp.rollout_stats_dict(st)
+        d["ms"] = ms
+        out[W_MISSIONS[m]] = d
+    return out
+
+
+W_MISSIONS = {0: "time", 1: "energy", 2: "net_energy"}
+
+
+def replan_leg(pl, w, p, env, vs, missions, reps: int = 3) -> dict:
+    """Re-planning after a forecast update at the middle layer: new coefficient
+    draws for layers t >= nt/2, then mdp_build_from (those layers only) +
+    mdp_value_iterate_layers (those layers only) + mdp_policy, against the full
+    step on the updated environment."""
+    import numpy as np
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    t0 = p["nt"] // 2
+    mu2 = w.mu.copy()
+    rng = np.random.default_rng(2718)
+    K, nr = mu2.shape[1], mu2.shape[2]
+    sig = (0.2 / np.arange(1, K + 1))[:, None]
+    mu2[t0:] = (sig * rng.standard_normal((p["nt"] - t0, K, nr))).astype(np.float32)
+    env2 = dict(env, mu=torch.from_numpy(mu2).to(pl.device))
+    m = missions[0]
+    model, st2 = pl.build(p, env2)  # a model sized for the updated environment (untimed)
+    assert st2["status"] == mdp.MDP_OK, st2
+    scratch = pl.scratch(p)
+    bst, vst = mdp.stats_buffer(mdp.MdpBuildStats), mdp.stats_buffer(mdp.MdpViStats)
+    pi = torch.empty(vs[0].numel(), dtype=torch.int32, device=pl.device)
+    s = torch.cuda.current_stream()
+    v = vs[0]
+
+    def replan():
+        mdp.mdp_build_from(pl.ctx, p, env2, model, t0, scratch, bst, s)
+        mdp.mdp_value_iterate_layers(pl.ctx, p, model, m, t0, 1e-6, 100000, v, scratch, vst, s)
+        mdp.mdp_policy(pl.ctx, p, model, m, v, pi, s)
+
+    def full():
+        mdp.mdp_build(pl.ctx, p, env2, model, scratch, bst, s)
+        v.zero_()
+        mdp.mdp_value_iterate(pl.ctx, p, model, m, 1e-6, 100000, v, scratch, vst, s)
+        mdp.mdp_policy(pl.ctx, p, model, m, v, pi, s)
+
+    full()  # warm, and the model now holds the updated build
+    ms_full = _ev_ms(s, full, reps)
+    ms_replan = _ev_ms(s, replan, reps)
+    b, vi = mdp.read_stats(bst, mdp.MdpBuildStats), mdp.read_stats(vst, mdp.MdpViStats)
+    assert b["status"] == mdp.MDP_OK and vi["status"] == mdp.MDP_OK, (b, vi)
+    return dict(t0=t0, mission=W_MISSIONS[m], ms_replan=ms_replan, ms_full=ms_full, speedup=ms_full / ms_replan,
+                rebuilt_samples=b["samples"], sweeps=vi["sweeps"])
+
+
+def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, near_edge: bool = False,
+             extras: bool = False) -> dict:
+    """Time `steps` planning steps of workload w (after `warmup` untimed ones):
+    build + value iteration of every mission + policies. Returns the step time,
+    the per-kernel rates and the rooflines of the build and the sweep; with
+    `extras`, also the policies' rollouts and a re-planning timing (untimed in
+    the step)."""
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    p = dict(w.problem)
+    if near_edge:
+        p["flags"] |= mdp.MDP_FLAG_NEAR_EDGE
+    missions = w.missions()
+    env = pl.upload_env(w)
+    tune = mdp.mdp_autotune(pl.ctx, p, env) if autotune else None  # untimed: the build launch shape
+    sizes = mdp.mdp_build_query(p)
+    model, st0 = pl.build(p, env)  # sizes the model (untimed)
+    assert st0["status"] == mdp.MDP_OK, st0
+    nnz = st0["nnz"]
+    del model
+    torch.cuda.empty_cache()
+    model = pl.alloc_model(p, nnz)
+    scratch = pl.scratch(p)
+    vi_scratch = torch.empty(len(missions) * sizes["scratch_bytes"], dtype=torch.uint8, device=pl.device)
+    ns = sizes["n_states"]
+    vs = [torch.zeros(ns, dtype=torch.float64, device=pl.device) for _ in missions]
+    pis = [torch.empty(ns, dtype=torch.int32, device=pl.device) for _ in missions]
+    bstat = mdp.stats_buffer(mdp.MdpBuildStats)
+    vsz = mdp.C.sizeof(mdp.MdpViStats)
+    vstat = torch.zeros(len(missions) * vsz, dtype=torch.uint8, pin_memory=True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mdp.mdp_build(pl.ctx, p, env, model, scratch, bstat, stream)
+        for v in vs:
+            v.zero_()
+        mdp.mdp_value_iterate_missions(pl.ctx, p, model, missions, 1e-6, 100000, vs, vi_scratch, vstat, stream)
+        for k, m in enumerate(missions):
+            mdp.mdp_policy(pl.ctx, p, model, m, vs[k], pis[k], stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] {label}: timing {steps} steps", file=sys.stderr, flush=True)
+    mdp.mdp_ctx_profile(pl.ctx, True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    mdp.mdp_ctx_profile(pl.ctx, False)
+    ms_step = ev0.elapsed_time(ev1) / steps
+    bs = mdp.read_stats(bstat, mdp.MdpBuildStats)
+    vst = [mdp.read_stats(vstat[k * vsz:(k + 1) * vsz], mdp.MdpViStats) for k in range(len(missions))]
+    assert bs["status"] == mdp.MDP_OK and all(v["status"] == mdp.MDP_OK for v in vst), (bs, vst)
+
+    kt = {k: mdp.mdp_ctx_profile_read(pl.ctx, k) for k in
+          (mdp.MDP_KERNEL_BUILD, mdp.MDP_KERNEL_VI_SWEEP, mdp.MDP_KERNEL_POLICY, mdp.MDP_KERNEL_COPY)}
+    n_b, ms_b = kt[mdp.MDP_KERNEL_BUILD]
+    n_v, ms_v = kt[mdp.MDP_KERNEL_VI_SWEEP]
+    nominal = w.nominal_samples
+    K, na = p["n_modes"], w.n_actions
+    rows = sizes["n_rows"]
+    build_s = ms_b / 1e3 / steps            # all passes of one build
+    build_launch_s = ms_b / 1e3 / n_b       # one launch (pass)
+    samples_launch = nominal / bs["n_slabs"]
+
+    # Build kernel (VALU-bound): algorithmic FP32 flops per sample are the X, Y
+    # adds of the landing (2) plus the 2K + 2 FMAs (2 flops each) of velocity
+    # synthesis and position per (layer, cell, realization), shared by the N_a
+    # actions. The measured VALU issue rate (SQ_INSTS_VALU x 64 lanes per launch,
+    # over the live launch time) is reported beside it against 3.93e13 lane-op/s.
+    flops_per_sample = 2.0 + 2.0 * (2.0 * K + 2.0) / na
+    ach_flops = flops_per_sample * samples_launch / build_launch_s
+    kname = "k_build"
+    valu = measured(kname, label, "valu_insts")
+    roof_build = dict(bound="alu", achieved=ach_flops / 1e12, peak=FP32_VECTOR / 1e12, unit="TFLOP/s",
+                      frac=ach_flops / FP32_VECTOR, traffic=measured_traffic(kname, label), kernel=kname,
+                      fp32_flops_per_sample=flops_per_sample, samples_per_launch=samples_launch,
+                      launch_ms=build_launch_s * 1e3,
+                      valu_lane_ops_per_sample_issued=None if valu is None else valu * 64 / samples_launch,
+                      valu_issue_frac=None if valu is None else valu * 64 / build_launch_s / VALU_LANE_OPS,
+                      valu_issue_peak_Tops=VALU_LANE_OPS / 1e12)
+    # VI (HBM-bound): compulsory bytes of the stored format for the layers each
+    # fused sweep recomputes (sweep k of a solve recomputes layers t < nt - k + 1):
+    # per layer 8 B row pointer per row and 6 B per nonzero, read once for all
+    # missions, plus per mission still iterating 4 B reward per row and v read
+    # and written once per state.
+    nt, nc = p["nt"], p["nx"] * p["ny"]
+    rp_layer = model["row_ptr"][:: nc * na].cpu().numpy()  # row_ptr at layer starts (+ end)
+    nnz_layer = rp_layer[1:] - rp_layer[:-1]
+    shared_bytes = 8 * nc * na + 6 * nnz_layer
+    mission_bytes = 4 * nc * na + 16 * nc
+    solve_bytes = 0
+    for k in range(max(v["sweeps"] for v in vst)):
+        live = sum(1 for v in vst if v["sweeps"] > k)
+        t_hi = max(0, min(nt, nt - k + 1))
+        solve_bytes += int(shared_bytes[:t_hi].sum() + live * mission_bytes * t_hi)
+    sweep_bytes = int(shared_bytes.sum() + len(missions) * mission_bytes * nt) + 8  # one full fused sweep
+    sweep_s = ms_v / 1e3 / n_v
+    ach_hbm = solve_bytes * steps / (ms_v / 1e3)
+    sweeps_per_step = sum(v["sweeps"] for v in vst)
+    vname = f"k_vi_sweep_missions<{len(missions)}>"
+    roof_vi = dict(bound="hbm", achieved=ach_hbm / 1e9, peak=HBM_BW / 1e9, unit="GB/s", frac=ach_hbm / HBM_BW,
+                   traffic=measured_traffic(vname, label), kernel=vname,
+                   algorithmic_bytes_per_launch=solve_bytes / max(1, n_v // steps), bytes_full_sweep=sweep_bytes,
+                   bytes_per_step=solve_bytes, launch_ms=sweep_s * 1e3)
+    out = dict(
+        workload=w.name, rows=rows, nnz=nnz, samples_per_step=nominal, missions=missions,
+        skipped_source_fraction=skipped_fraction(w), near_edge_counted=bool(near_edge),
+        ms_per_step=ms_step, samples_per_s=nominal / (ms_step / 1e3),
+        build_samples_per_s=nominal / build_s, build_ms=build_s * 1e3, build_launches_per_step=n_b // steps,
+        vi_sweeps_per_s=sweeps_per_step * steps / (ms_v / 1e3),  # mission sweeps
+        vi_launches_per_s=1e3 / (ms_v / n_v),  # fused sweeps (all missions)
+        vi_sweeps_per_step=sweeps_per_step, vi_ms_per_step=ms_v / steps,
+        policy_ms_per_step=kt[mdp.MDP_KERNEL_POLICY][1] / steps, copy_ms_per_step=kt[mdp.MDP_KERNEL_COPY][1] / steps,
+        build_shape=(None if tune is None else dict(tune["shapes"][tune["best"]], sample_layers=tune["sample_layers"],
+                                                     default_ms=tune["shapes"][tune["default"]]["ms"])),
+        rooflines={"build": roof_build, "vi_sweep": roof_vi},
+        dominant="build" if ms_b >= ms_v else "vi_sweep",
+    )
+    if extras:
+        out["rollouts"] = rollout_leg(pl, w, p, env, pis, missions)
+        if len(missions) == 1:
+            out["replan"] = replan_leg(pl, w, p, env, vs, missions)
+    del model, scratch, vi_scratch, vs, pis
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(pl, n_inst: int = 64, reps: int = 2) -> dict:
@@ -229,6 +479,7 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_sh
         pass
     srv.poll()
     first_step = srv.info()["steps"]  # step numbers continue after the warm-up
+    print(f"[bench] served: {n} requests over {seconds:.0f} s", file=sys.stderr, flush=True)
     lat, status, admit = {}, {}, {}
     step_start = {}  # step number -> host time it started
     i, n_steps, t_steps = 0, 0, 0.0
@@ -265,6 +516,7 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_sh
                     sweeps_per_step=sweeps_per_step)
 
     # sequential plain solves of the same trace
+    print("[bench] served trace: sequential plain solves", file=sys.stderr, flush=True)
     lat2 = {}
     bst, vst = mdp.stats_buffer(mdp.MdpBuildStats), mdp.stats_buffer(mdp.MdpViStats)
     with torch.cuda.stream(s):
@@ -295,16 +547,33 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_sh
                 p50_speedup=seq["p50_ms"] / served["p50_ms"], p99_speedup=seq["p99_ms"] / served["p99_ms"])
 
 
+HEADLINE = "large"
+
+
+def workload(name: str):
+    from paper_2109_00857_amd import workloads as W
+
+    if name == "paper_actions":  # the paper's application action set: 16 headings x 2 speeds
+        w = W.config2()
+        w.problem["n_speed"] = 2
+        w.name = "c2_paper_actions"
+        return w
+    return {"large": W.config3, "paper_shaped": W.config2}[name]()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["large", "paper_shaped"], default=HEADLINE,
+                    help="instance of the headline step (default: the 200x200x200 large instance)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--near-edge", action="store_true", help="also count near-edge samples")
+    ap.add_argument("--no-second", action="store_true", help="skip the second single-instance workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-trace leg")
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the served trace")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the served trace")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrival rate (per second)")
     ap.add_argument("--build-share", type=int, default=100,
                     help="percent of the GPU's resident workgroups a served build batch may hold")
@@ -328,147 +597,64 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    from paper_2109_00857_amd import mdp
 
-    from paper_2109_00857_amd import mdp, workloads as W
-
-    w = W.config2()
-    p = dict(w.problem)
-    if args.near_edge:
-        p["flags"] |= mdp.MDP_FLAG_NEAR_EDGE
-    missions = w.missions()
     pl = mdp.Planner(0)
-    env = pl.upload_env(w)
-    tune = None
-    if not args.no_autotune:  # untimed: pick the build launch shape for this shape class
-        tune = mdp.mdp_autotune(pl.ctx, p, env)
-    sizes = mdp.mdp_build_query(p)
-    model, st0 = pl.build(p, env)  # sizes the model (untimed)
-    assert st0["status"] == mdp.MDP_OK, st0
-    nnz = st0["nnz"]
-    model = pl.alloc_model(p, nnz)
-    scratch = pl.scratch(p)
-    vi_scratch = torch.empty(len(missions) * sizes["scratch_bytes"], dtype=torch.uint8, device=pl.device)
-    ns = sizes["n_states"]
-    vs = [torch.zeros(ns, dtype=torch.float64, device=pl.device) for _ in missions]
-    pis = [torch.empty(ns, dtype=torch.int32, device=pl.device) for _ in missions]
-    bstat = mdp.stats_buffer(mdp.MdpBuildStats)
-    vsz = mdp.C.sizeof(mdp.MdpViStats)
-    vstat = torch.zeros(len(missions) * vsz, dtype=torch.uint8, pin_memory=True)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        mdp.mdp_build(pl.ctx, p, env, model, scratch, bstat, stream)
-        for v in vs:
-            v.zero_()
-        mdp.mdp_value_iterate_missions(pl.ctx, p, model, missions, 1e-6, 100000, vs, vi_scratch, vstat, stream)
-        for k, m in enumerate(missions):
-            mdp.mdp_policy(pl.ctx, p, model, m, vs[k], pis[k], stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    mdp.mdp_ctx_profile(pl.ctx, True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    mdp.mdp_ctx_profile(pl.ctx, False)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    bs = mdp.read_stats(bstat, mdp.MdpBuildStats)
-    vst = [mdp.read_stats(vstat[k * vsz:(k + 1) * vsz], mdp.MdpViStats) for k in range(len(missions))]
-    assert bs["status"] == mdp.MDP_OK and all(v["status"] == mdp.MDP_OK for v in vst), (bs, vst)
-
-    kt = {k: mdp.mdp_ctx_profile_read(pl.ctx, k) for k in
-          (mdp.MDP_KERNEL_BUILD, mdp.MDP_KERNEL_VI_SWEEP, mdp.MDP_KERNEL_POLICY, mdp.MDP_KERNEL_COPY)}
-    n_b, ms_b = kt[mdp.MDP_KERNEL_BUILD]
-    n_v, ms_v = kt[mdp.MDP_KERNEL_VI_SWEEP]
-    nominal = w.nominal_samples
-    K, na = p["n_modes"], w.n_actions
-    rows, nst = sizes["n_rows"], sizes["n_states"]
-
-    # Build kernel: algorithmic VALU lane-ops per sample = X, Y adds and the two
-    # floor conversions of cell() (4), plus the 2K + 2 FMAs of velocity synthesis
-    # and position per (layer, cell, realization) shared by the N_a actions.
-    ops_per_sample = 4.0 + (2.0 * K + 2.0) / na
-    builds = n_b // max(1, bs["n_slabs"])
-    build_ops = ops_per_sample * nominal
-    build_s = ms_b / 1e3 / builds           # all passes of one build
-    build_launch_s = ms_b / 1e3 / n_b       # one launch
-    ach_alu = build_ops / bs["n_slabs"] / build_launch_s
-    # VI: compulsory bytes of the stored format for the layers each fused sweep
-    # recomputes (sweep k of a solve recomputes layers t < nt - k + 1): per
-    # layer 8 B row pointer per row and 6 B per nonzero, read once for all
-    # missions, plus per mission still iterating 4 B reward per row and v read
-    # and written once per state.
-    nt, nc = p["nt"], p["nx"] * p["ny"]
-    rp_layer = model["row_ptr"][:: nc * na].cpu().numpy()  # row_ptr at layer starts (+ end)
-    nnz_layer = rp_layer[1:] - rp_layer[:-1]
-    shared_bytes = 8 * nc * na + 6 * nnz_layer
-    mission_bytes = 4 * nc * na + 16 * nc
-    solve_bytes = 0
-    for k in range(max(v["sweeps"] for v in vst)):
-        live = sum(1 for v in vst if v["sweeps"] > k)
-        t_hi = max(0, min(nt, nt - k + 1))
-        solve_bytes += int(shared_bytes[:t_hi].sum() + live * mission_bytes * t_hi)
-    sweep_bytes = int(shared_bytes.sum() + len(missions) * mission_bytes * nt) + 8  # one full fused sweep
-    sweep_s = ms_v / 1e3 / n_v
-    ach_hbm = solve_bytes * args.steps / (ms_v / 1e3)
-    sweeps_per_step = sum(v["sweeps"] for v in vst)
-
-    roof_build = dict(bound="alu", achieved=ach_alu / 1e12, peak=VALU_LANE_OPS / 1e12, unit="Top/s",
-                      frac=ach_alu / VALU_LANE_OPS, traffic=measured_traffic("k_build"),
-                      kernel="k_build", ops_per_sample=ops_per_sample,
-                      launch_ms=build_launch_s * 1e3, fp32_flops_frac=None)
-    # FP32 arithmetic share: 2 adds + (2K+2) FMAs (2 flops) per N_a samples
-    flops = (2.0 + 2.0 * (2.0 * K + 2.0) / na) * nominal / bs["n_slabs"]
-    roof_build["fp32_flops_frac"] = flops / build_launch_s / FP32_VECTOR
-    roof_vi = dict(bound="hbm", achieved=ach_hbm / 1e9, peak=HBM_BW / 1e9, unit="GB/s",
-                   frac=ach_hbm / HBM_BW, traffic=measured_traffic("k_vi_sweep_missions<3>"),
-                   kernel="k_vi_sweep_missions<3>", algorithmic_bytes_per_launch=solve_bytes / max(1, n_v // args.steps),
-                   bytes_full_sweep=sweep_bytes, bytes_per_step=solve_bytes, launch_ms=sweep_s * 1e3)
-    dominant = roof_build if ms_b >= ms_v else roof_vi
-
+    w = workload(args.workload)
+    print(f"[bench] headline workload {args.workload}: {w.n_rows} rows, {w.nominal_samples:.3e} samples",
+          file=sys.stderr, flush=True)
+    main_leg = step_leg(pl, w, args.workload, args.steps, args.warmup, autotune=not args.no_autotune,
+                        near_edge=args.near_edge, extras=not args.no_second)
+    rf = main_leg["rooflines"]
+    descr = {"large": "large single instance: 200x200 cells, 200 layers, 16 modes, 10000 AR(1) realizations, "
+                      "32 headings, 7x7 sub-grid, 4 moving discs, net-energy mission",
+             "paper_shaped": "paper-shaped single instance: 100x100 cells, 120 layers, 10 modes, 5000 AR(1) "
+                             "realizations, 16 headings, 5x5 sub-grid, 4 moving discs, time + energy + net-energy "
+                             "missions"}
     out = {
         "metric": "MDP build samples/s + VI sweeps/s (% roofline); p50/p99 plan latency served",
-        "value": nominal / (ms_step / 1e3),
+        "value": main_leg["samples_per_s"],
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 landings, f64 values",
         "data": "synthetic",
-        "config": {"workload": "paper-shaped single instance: 100x100 cells, 120 layers, 10 modes, "
-                               "5000 AR(1) realizations, 16 headings, 5x5 sub-grid, 4 moving discs, "
-                               "time + energy + net-energy missions",
-                   "rows": rows, "nnz": nnz, "samples_per_step": nominal,
-                   "near_edge_counted": bool(args.near_edge)},
-        "build_samples_per_s": nominal / build_s,
-        "build_ms": build_s * 1e3,
-        "vi_sweeps_per_s": sweeps_per_step * args.steps / (ms_v / 1e3),  # mission sweeps
-        "vi_launches_per_s": 1e3 / (ms_v / n_v),  # fused sweeps (all missions)
-        "vi_sweeps_per_step": sweeps_per_step,
-        "vi_ms_per_step": ms_v / args.steps,
-        "policy_ms_per_step": kt[mdp.MDP_KERNEL_POLICY][1] / args.steps,
-        "copy_ms_per_step": kt[mdp.MDP_KERNEL_COPY][1] / args.steps,
-        "build_shape": (None if tune is None else dict(tune["shapes"][tune["best"]], sample_layers=tune["sample_layers"],
-                                                        default_ms=tune["shapes"][tune["default"]]["ms"])),
-        "roofline": dominant,
-        "rooflines": {"build": roof_build, "vi_sweep": roof_vi},
+        "config": {"workload": descr[args.workload], "rows": main_leg["rows"], "nnz": main_leg["nnz"],
+                   "samples_per_step": main_leg["samples_per_step"],
+                   "skipped_source_fraction": main_leg["skipped_source_fraction"],
+                   "near_edge_counted": main_leg["near_edge_counted"]},
+        "build_samples_per_s": main_leg["build_samples_per_s"],
+        "build_ms": main_leg["build_ms"],
+        "vi_sweeps_per_s": main_leg["vi_sweeps_per_s"],
+        "vi_launches_per_s": main_leg["vi_launches_per_s"],
+        "vi_sweeps_per_step": main_leg["vi_sweeps_per_step"],
+        "vi_ms_per_step": main_leg["vi_ms_per_step"],
+        "policy_ms_per_step": main_leg["policy_ms_per_step"],
+        "copy_ms_per_step": main_leg["copy_ms_per_step"],
+        "build_shape": main_leg["build_shape"],
+        "roofline": rf[main_leg["dominant"]],
+        "rooflines": rf,
     }
-    del model, scratch, vs, pis
-    torch.cuda.empty_cache()
+    for k in ("rollouts", "replan"):
+        if k in main_leg:
+            out[k] = main_leg[k]
+    if not args.no_second:
+        other = "paper_shaped" if args.workload == "large" else "large"
+        for name in (other, "paper_actions"):
+            try:
+                out[name] = step_leg(pl, workload(name), name, args.steps, args.warmup,
+                                     autotune=not args.no_autotune, near_edge=args.near_edge, extras=True)
+            except Exception as e:  # reported, never hides the main line
+                out[name] = {"error": repr(e)}
     if not args.no_batched:
         try:
             out["batched"] = batched_leg(pl)
-        except Exception as e:  # reported, never hides the main line
+        except Exception as e:
             out["batched"] = {"error": repr(e)}
     if not args.no_served:
         try:

@@ -57,6 +57,14 @@ typedef int32_t mdp_status;
 #define MDP_MISSION_NET_ENERGY 2 /* R = E[-c_f F^2 + c_r (g(s) + g(s'))/2] dt    */
 
 #define MDP_FLAG_NEAR_EDGE 1u /* count samples within 1e-6 (physical) of an edge */
+/* Swept-path obstacle test (the path reading of Alg. 2's "obstacle between s
+ * and s'"): a landing is DEAD (r_outbound) when the straight step from the
+ * source cell centre to the landing point enters the interior of a cell, other
+ * than the source cell, that is an obstacle at t+1; without the flag only the
+ * landing cell is checked. Used by mdp_build, mdp_build_from and mdp_rollout;
+ * batches and servers refuse it (MDP_E_INVALID). A row may then hold one entry
+ * more than its sub-grid has cells: nnz_upper = rows * min(N_sg + 1, n_real). */
+#define MDP_FLAG_SWEPT_PATH 2u
 
 #define MDP_MAX_ACTIONS 64
 #define MDP_MAX_MODES 16
@@ -172,6 +180,30 @@ mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env,
                      const mdp_model *model, void *scratch, size_t scratch_bytes,
                      mdp_build_stats *stats, void *stream);
 
+/* Incremental re-planning (the paper's in-mission updates of the forecast,
+ * Sec. I and Sec. V): rebuild, in place, the rows of the decision layers
+ * [t0, nt) of a model that holds a complete build of the same problem, after
+ * the environment changed from layer t0 on (new coefficients mu[t >= t0], new
+ * mean or modes at t >= t0, new mask or scalar field at layers > t0). The rows
+ * of layers < t0 and their entries are kept; the rebuilt entries follow them,
+ * so the result equals mdp_build on the new environment bit for bit as long
+ * as the rows of layers < t0 did not change (a layer-(t0-1) row reads the mask
+ * and scalar field of layer t0: rebuild from t0 - 1 when those changed).
+ * stats->samples counts the rebuilt layers' landings and stats->nnz the whole
+ * model's nonzeros (MDP_E_CAPACITY above nnz_capacity). Same scratch as
+ * mdp_build. */
+mdp_status mdp_build_from(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
+                          int32_t t0, void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream);
+
+/* Wait for `stream` to reach the end of an mdp_build and return the device
+ * status it reported (Alg. 1 ENSURE: the model is complete only once this is
+ * MDP_OK). `stats` is the host struct passed to that mdp_build. Returns
+ * MDP_OK, MDP_E_CAPACITY (stats->nnz is the capacity needed), MDP_E_SUBGRID
+ * (stats->n_escape landings left the sub-grid; the model is not valid), or
+ * MDP_E_HIP if the stream reported an error; the last error text names the
+ * figures. */
+mdp_status mdp_build_sync(mdp_ctx *ctx, const mdp_build_stats *stats, void *stream);
+
 /* Synchronous (Jacobi) value iteration on the model of mission `mission`
  * (Sec. II-B update rule), from the values in d_v (v0; zeros for a cold start)
  * until max_s |v_k - v_{k-1}| < tol or max_sweeps sweeps. Values are fp64,
@@ -182,6 +214,17 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
                              int32_t mission, double tol, int32_t max_sweeps, double *d_v,
                              void *scratch, size_t scratch_bytes, mdp_vi_stats *stats,
                              void *stream);
+
+/* Value iteration of the decision layers [t_first, nt) only (re-planning from
+ * layer t_first on: every transition goes from layer t to t + 1 or to a sink,
+ * so those layers depend on nothing earlier). The values of layers < t_first
+ * in d_v are left as they are; those of layers >= t_first end up equal to
+ * mdp_value_iterate's from the same v0, bit for bit, after at most
+ * nt - t_first + 1 sweeps (stats count these sweeps and their residuals, over
+ * the layers solved). Same scratch as mdp_value_iterate. */
+mdp_status mdp_value_iterate_layers(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
+                                    int32_t t_first, double tol, int32_t max_sweeps, double *d_v, void *scratch,
+                                    size_t scratch_bytes, mdp_vi_stats *stats, void *stream);
 
 /* mdp_value_iterate for n_missions (1..3) distinct missions of one model in
  * one solve (Sec. II-B update rule per mission). Each sweep reads the model's
@@ -203,6 +246,55 @@ mdp_status mdp_value_iterate_missions(mdp_ctx *ctx, const mdp_problem *p, const 
  * d_pi int32 [N_s]. */
 mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
                       int32_t mission, const double *d_v, int32_t *d_pi, void *stream);
+
+/* ------------------------------------------------------------------ rollouts
+ * The policy applied to every realization of the stochastic flow (Sec. IV:
+ * each optimal policy is followed through the ensemble of flow fields, giving
+ * the distribution of paths, the expected travel time and energy).
+ * In realization r the agent starts in (start_i, start_j) at t = 0; at layer t
+ * in cell c it takes action pi[t][c] and lands where realization r's flow
+ * puts it, computed with the FP32 operations of mdp_build (so every landing is
+ * a sample of the transition model). The landing ends the path outside the
+ * domain or on an obstacle at t+1 (reward r_outbound), on the target (base +
+ * r_term, arrived) or beyond the horizon (r_outbound); otherwise the path goes
+ * on with reward base (Table I, Eqs. Rsa_time / Rsa_energyConsumption /
+ * Rsa_NetEnergy with the mean scalar field). A path starting on the target has
+ * arrived after 0 steps (return 0); one starting in an obstacle ends at once
+ * with return r_outbound. */
+#define MDP_ROLL_ARRIVED 0
+#define MDP_ROLL_OUTBOUND 1
+#define MDP_ROLL_OBSTACLE 2
+#define MDP_ROLL_HORIZON 3
+typedef struct mdp_rollout_path {
+  int32_t outcome;  /* MDP_ROLL_*                                                */
+  int32_t steps;    /* decisions taken                                           */
+  double ret[3];    /* realized return of missions time, energy, net energy      */
+  double energy;    /* energy expended, sum of c_f F^2 dt over the steps         */
+  double fsum;      /* sum of the speeds of the actions taken                    */
+} mdp_rollout_path;
+typedef struct mdp_rollout_stats {
+  int64_t n_real, n_arrived, n_outbound, n_obstacle, n_horizon;
+  double p_reach;                 /* n_arrived / n_real                        */
+  double mean_time_arrived;       /* mean steps * dt over the arrived paths    */
+  double mean_energy_arrived;     /* mean energy expended over arrived paths   */
+  double mean_net_energy_arrived; /* mean net energy consumed (expended minus
+                                     harvested from the mean scalar field)     */
+  double mean_speed_arrived;      /* speed sum / steps over the arrived paths  */
+  double mean_return[3];          /* mean realized return over all paths       */
+} mdp_rollout_stats;
+/* Device scratch bytes of mdp_rollout for problem p (host only). */
+mdp_status mdp_rollout_query(const mdp_problem *p, size_t *scratch_bytes);
+/* Roll the policy d_pi (int32 [nt][ny][nx], device; entries outside [0, N_a)
+ * are read as action 0) out in all n_real realizations of env (device
+ * pointers as for mdp_build; gbar may be NULL, then the net-energy return has
+ * no harvest term). d_traj: int32 [nt+1][n_real] device, layer-major (the
+ * cell index at each layer, the target cell at the arrival layer, -1 after the
+ * end), or NULL. d_paths: [n_real] device, or NULL (then kept in scratch).
+ * stats: host, written when the stream reaches the end of the call. Errors:
+ * MDP_E_INVALID (pointers, problem), MDP_E_SCRATCH. */
+mdp_status mdp_rollout(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const int32_t *d_pi,
+                       int32_t *d_traj, mdp_rollout_path *d_paths, void *scratch, size_t scratch_bytes,
+                       mdp_rollout_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------ batches
  * Many independent problems built and solved together (not in the paper: the
@@ -273,6 +365,11 @@ typedef struct mdp_server_config {
                               may hold (1..100; 0 = 100); the rest keeps
                               sweeping the admitted requests meanwhile          */
   double tol;              /* residual below which a request has converged      */
+  double chunk_cost;       /* build work per launch of a served build, in
+                              landings (each plus a quarter per mode term per
+                              action); 0 = 6e9 (about 2 ms on an MI355X)        */
+  double large_cost;       /* requests whose build cost (same unit) exceeds this
+                              build on the large-request lane; 0 = 3e10         */
 } mdp_server_config;
 typedef struct mdp_served {
   int64_t tag;                   /* the submitter's tag                         */

@@ -71,6 +71,9 @@ int popcount3(uint32_t m) { return (int)(m & 1) + (int)(m >> 1 & 1) + (int)(m >>
 // Launch plan of one problem (pure host arithmetic).
 struct Plan {
   int na, nc, nsg, W;
+  bool swept;   // MDP_FLAG_SWEPT_PATH: one more histogram bin (swept-path DEAD)
+  int nbins;    // histogram bins: nsg, plus one with the swept-path test
+  int max_row;  // most entries of a row: min(nbins, n_real)
   int row_lanes, hw, cells_per_tile, tiles_per_layer, rch;
   bool pack16;
   int kmax;
@@ -115,12 +118,12 @@ std::vector<PlanChoice> plan_candidates(const mdp_problem *p)
 {
   std::vector<PlanChoice> out;
   const int na = p->n_head * p->n_speed;
-  const int nsg = (2 * p->sub_hx + 1) * (2 * p->sub_hy + 1);
+  const int nbins = (2 * p->sub_hx + 1) * (2 * p->sub_hy + 1) + ((p->flags & MDP_FLAG_SWEPT_PATH) ? 1 : 0);
   for (int rl = kBlock; rl >= 64; rl /= 2) {
     if (rl < na) break;
     for (int rch = 64; rch <= 256; rch *= 2)
       for (int pk = 1; pk >= 0; --pk)
-        if (plan_lds(nsg, na, rl, rch, pk != 0) <= kLdsLimit) {
+        if (plan_lds(nbins, na, rl, rch, pk != 0) <= kLdsLimit) {
           PlanChoice c;
           c.row_lanes = rl;
           c.rch = rch;
@@ -154,6 +157,9 @@ const char *make_plan(const mdp_problem *p, Plan &pl, const PlanChoice *choice =
   pl.nc = p->nx * p->ny;
   pl.W = 2 * p->sub_hx + 1;
   pl.nsg = pl.W * (2 * p->sub_hy + 1);
+  pl.swept = (p->flags & MDP_FLAG_SWEPT_PATH) != 0;
+  pl.nbins = pl.nsg + (pl.swept ? 1 : 0);
+  pl.max_row = std::min(pl.nbins, p->n_real);
   pl.rows = (int64_t)p->nt * pl.nc * pl.na;
   pl.kmax = mode_bound(p->n_modes);
   bool ok = false;
@@ -162,7 +168,7 @@ const char *make_plan(const mdp_problem *p, Plan &pl, const PlanChoice *choice =
     if ((rl == 64 || rl == 128 || rl == 256) && rl >= pl.na && (choice->rch == 64 || choice->rch == 128 ||
                                                                  choice->rch == 256)) {
       pl.pack16 = choice->pack16 != 0;
-      pl.lds = plan_lds(pl.nsg, pl.na, rl, choice->rch, pl.pack16);
+      pl.lds = plan_lds(pl.nbins, pl.na, rl, choice->rch, pl.pack16);
       if (pl.lds <= kLdsLimit) {
         pl.row_lanes = rl;
         pl.hw = pl.pack16 ? rl / 2 : rl;
@@ -178,7 +184,7 @@ const char *make_plan(const mdp_problem *p, Plan &pl, const PlanChoice *choice =
     if (rl < pl.na) break;
     const int cells = std::min(rl / pl.na, 32);
     const int rch = cells <= 8 ? 256 : (cells <= 16 ? 128 : 64);
-    const size_t lds = plan_lds(pl.nsg, pl.na, rl, rch, true);
+    const size_t lds = plan_lds(pl.nbins, pl.na, rl, rch, true);
     if (lds <= kLdsLimit) {
       pl.row_lanes = rl;
       pl.hw = rl / 2;
@@ -190,7 +196,7 @@ const char *make_plan(const mdp_problem *p, Plan &pl, const PlanChoice *choice =
   }
   if (!ok) return "sub-grid too large for the LDS histogram";
   pl.tiles_per_layer = (pl.nc + pl.cells_per_tile - 1) / pl.cells_per_tile;
-  pl.wg_cap = (int64_t)pl.cells_per_tile * pl.na * std::min(pl.nsg, p->n_real);
+  pl.wg_cap = (int64_t)pl.cells_per_tile * pl.na * pl.max_row;
   if (pl.wg_cap < 1) pl.wg_cap = 1;
   const size_t rows_per_layer = (size_t)pl.nc * pl.na;
   const size_t per_layer = (size_t)pl.tiles_per_layer * pl.wg_cap * 8;
@@ -321,6 +327,7 @@ void fill_params(const mdp_problem *p, const mdp_env *env, const mdp_model *mode
   P.hy = p->sub_hy;
   P.W = pl.W;
   P.nsg = pl.nsg;
+  P.nbins = pl.nbins;
   P.ti = p->target_i;
   P.tj = p->target_j;
   P.mean_tstride = p->mean_time_varying ? pl.nc : 0;
@@ -482,7 +489,7 @@ mdp_status mdp_build_query(const mdp_problem *p, mdp_sizes *out)
   out->n_actions = pl.na;
   out->n_rows = pl.rows;
   out->n_sg = pl.nsg;
-  out->nnz_upper = pl.rows * (int64_t)std::min(pl.nsg, p->n_real);
+  out->nnz_upper = pl.rows * (int64_t)pl.max_row;
   out->n_missions = popcount3(p->mission_mask);
   size_t build_bytes = pl.build_bytes;  // enough for any launch shape a context may use
   for (const PlanChoice &c : plan_candidates(p)) {
@@ -552,7 +559,7 @@ mdp_status mdp_subgrid_auto(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *e
 
 static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
                                   void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream,
-                                  const Plan &pl);
+                                  const Plan &pl, int t_begin = 0);
 
 mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
                      void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream)
@@ -566,9 +573,29 @@ mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, con
   return build_with_plan(ctx, p, env, model, scratch, scratch_bytes, stats, stream, pl);
 }
 
+mdp_status mdp_build_from(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
+                          int32_t t0, void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream)
+{
+  if (!ctx) return MDP_E_INVALID;
+  Plan pl;
+  if (const char *e = ctx_plan(ctx, p, pl)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  if (t0 < 0 || t0 >= p->nt) {
+    set_err(ctx, "t0 must be in [0, nt)");
+    return MDP_E_INVALID;
+  }
+  return build_with_plan(ctx, p, env, model, scratch, scratch_bytes, stats, stream, pl, t0);
+}
+
+// Build of the layers [t_begin, nt) (all of them for mdp_build). With
+// t_begin > 0 the entries of the earlier layers stay where they are and the
+// rebuilt layers' entries follow them (the running count starts at the row
+// pointer of layer t_begin's first row).
 static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
                                   void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream,
-                                  const Plan &pl)
+                                  const Plan &pl, int t_begin)
 {
   if (const char *e = check_env(p, env)) {
     set_err(ctx, "%s", e);
@@ -595,7 +622,9 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
   BuildState *st = (BuildState *)sc;
   P.tab = (const float *)(sc + pl.tab_off);
   hipError_t e;
-  if ((e = launch_build_init(st, s)) != hipSuccess) return hip_fail(ctx, e, "init");
+  if ((e = t_begin > 0 ? launch_build_init_from(st, model->row_ptr + (int64_t)t_begin * pl.nc * pl.na, s)
+                       : launch_build_init(st, s)) != hipSuccess)
+    return hip_fail(ctx, e, "init");
   if ((e = launch_fill_tab(T, (float *)(sc + pl.tab_off), s)) != hipSuccess) return hip_fail(ctx, e, "tables");
   const bool near = (p->flags & MDP_FLAG_NEAR_EDGE) != 0;
   // A sub-grid that cannot hold the agent's own displacement cannot be
@@ -611,7 +640,7 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
     if ((e = launch_escape_only(P, st, s)) != hipSuccess) return hip_fail(ctx, e, "escape_only");
   } else {
     ModelOut M{model->row_ptr, model->col, model->cnt, model->nnz_capacity};
-    for (int t0 = 0; t0 < p->nt; t0 += pl.layers_per_slab, ++n_slabs) {
+    for (int t0 = t_begin; t0 < p->nt; t0 += pl.layers_per_slab, ++n_slabs) {
       SlabParams S;
       S.t0 = t0;
       S.nlayers = std::min(pl.layers_per_slab, p->nt - t0);
@@ -626,7 +655,7 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
       const int n_wg = S.nlayers * pl.tiles_per_layer;
       {
         Timed tm(ctx, MDP_KERNEL_BUILD, s);
-        if ((e = launch_build_slab(P, S, pl.kmax, pl.pack16, near, pl.lds, s)) != hipSuccess)
+        if ((e = launch_build_slab(P, S, pl.kmax, pl.pack16, near, pl.swept, pl.lds, s)) != hipSuccess)
           return hip_fail(ctx, e, "build");
       }
       const bool last = t0 + S.nlayers >= p->nt;
@@ -643,6 +672,25 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
   if ((e = hipMemcpyAsync(stats, &st->out, sizeof(mdp_build_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(ctx, e, "stats copy");
   return MDP_OK;
+}
+
+mdp_status mdp_build_sync(mdp_ctx *ctx, const mdp_build_stats *stats, void *stream)
+{
+  if (!ctx || !stats) return MDP_E_INVALID;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "build sync");
+  switch (stats->status) {
+    case MDP_OK: return MDP_OK;
+    case MDP_E_CAPACITY:
+      set_err(ctx, "the model needs %lld nonzeros", (long long)stats->nnz);
+      return MDP_E_CAPACITY;
+    case MDP_E_SUBGRID:
+      set_err(ctx, "%lld landings left the sub-grid", (long long)stats->n_escape);
+      return MDP_E_SUBGRID;
+    default:
+      set_err(ctx, "build reported status %d", (int)stats->status);
+      return stats->status;
+  }
 }
 
 // Sweep parameters of mission `mission` of a built model.
@@ -668,7 +716,7 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
   V.blocks_per_layer = (pl.nc + V.states_per_wg - 1) / V.states_per_wg;
   V.n_blocks = (int64_t)p->nt * V.blocks_per_layer;
   V.win_rows = vi_window_rows(p->nx, p->ny, p->sub_hy, V.states_per_wg);
-  V.max_row = std::min(pl.nsg, p->n_real);
+  V.max_row = pl.max_row;
   V.n_wg = n_wg;
   V.inv_nr = 1.0 / (double)p->n_real;
 }
@@ -699,7 +747,7 @@ static const char *tune_layout(const mdp_problem *q, TuneLayout &T)
   Plan pl;
   if (const char *e = make_plan(q, pl)) return e;
   T.rows = pl.rows;
-  T.cap = pl.rows * (int64_t)std::min(pl.nsg, q->n_real);
+  T.cap = pl.rows * (int64_t)pl.max_row;
   T.build_bytes = pl.build_bytes;
   for (const PlanChoice &c : plan_candidates(q)) {
     Plan x;
@@ -899,6 +947,52 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   return MDP_OK;
 }
 
+mdp_status mdp_value_iterate_layers(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
+                                    int32_t t_first, double tol, int32_t max_sweeps, double *d_v, void *scratch,
+                                    size_t scratch_bytes, mdp_vi_stats *stats, void *stream)
+{
+  Plan pl;
+  VIParams V;
+  mdp_status rc = vi_setup(ctx, p, model, mission, pl, V);
+  if (rc != MDP_OK) return rc;
+  if (t_first < 0 || t_first >= p->nt) {
+    set_err(ctx, "t_first must be in [0, nt)");
+    return MDP_E_INVALID;
+  }
+  if (!is_device_ptr(d_v) || !stats || max_sweeps < 0) {
+    set_err(ctx, "d_v must be a device pointer, stats non-NULL, max_sweeps >= 0");
+    return MDP_E_INVALID;
+  }
+  if (!is_device_ptr(scratch) || scratch_bytes < pl.vi_bytes) {
+    set_err(ctx, "scratch needs %zu device bytes", pl.vi_bytes);
+    return MDP_E_SCRATCH;
+  }
+  char *sc = (char *)scratch;
+  V.st = (VIState *)sc;
+  V.t_lo = t_first;
+  mdp_vi_stats *dstats = (mdp_vi_stats *)(sc + align_up(sizeof(VIState)));
+  double *v_alt = (double *)(sc + align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)));
+  double *wg_res = (double *)((char *)v_alt + align_up((size_t)V.ns * 8));
+  V.tol = tol;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = launch_vi_init(V.st, 1, s)) != hipSuccess) return hip_fail(ctx, e, "vi init");
+  // Layers [t_first, nt) depend only on each other: nt - t_first + 1 sweeps at most.
+  int n = max_sweeps;
+  if (tol > 0.0) n = std::min(n, p->nt - t_first + 1);
+  for (int k = 0; k < n; ++k) {
+    const double *vin = (k & 1) ? v_alt : d_v;
+    double *vout = (k & 1) ? d_v : v_alt;
+    Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
+    if ((e = launch_vi_sweep(V, vin, vout, vi_active_layers(p->nt, k), wg_res, s)) != hipSuccess)
+      return hip_fail(ctx, e, "vi sweep");
+  }
+  if ((e = launch_vi_finish(V, d_v, v_alt, dstats, s)) != hipSuccess) return hip_fail(ctx, e, "vi finish");
+  if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_vi_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(ctx, e, "vi stats copy");
+  return MDP_OK;
+}
+
 mdp_status mdp_value_iterate_missions(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,
                                       int32_t n_missions, const int32_t *missions, double tol, int32_t max_sweeps,
                                       double *const *d_v, void *scratch, size_t scratch_bytes, mdp_vi_stats *stats,
@@ -982,6 +1076,90 @@ mdp_status mdp_policy(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model
   return MDP_OK;
 }
 
+mdp_status mdp_rollout_query(const mdp_problem *p, size_t *scratch_bytes)
+{
+  if (!scratch_bytes) return MDP_E_INVALID;
+  if (check_problem(p)) return MDP_E_INVALID;
+  *scratch_bytes = align_up(sizeof(mdp_rollout_stats)) + align_up(sizeof(mdp_rollout_path) * (size_t)p->n_real);
+  return MDP_OK;
+}
+
+mdp_status mdp_rollout(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const int32_t *d_pi,
+                       int32_t *d_traj, mdp_rollout_path *d_paths, void *scratch, size_t scratch_bytes,
+                       mdp_rollout_stats *stats, void *stream)
+{
+  if (!ctx) return MDP_E_INVALID;
+  if (const char *e = check_problem(p)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  mdp_problem q = *p;
+  q.mission_mask &= ~(1u << MDP_MISSION_NET_ENERGY);  // gbar is optional here
+  if (q.mission_mask == 0) q.mission_mask = 1u;
+  if (const char *e = check_env(&q, env)) {
+    set_err(ctx, "%s", e);
+    return MDP_E_INVALID;
+  }
+  if (p->start_i < 0 || p->start_i >= p->nx || p->start_j < 0 || p->start_j >= p->ny) {
+    set_err(ctx, "start outside the grid");
+    return MDP_E_INVALID;
+  }
+  if (!is_device_ptr(d_pi) || (d_traj && !is_device_ptr(d_traj)) || (d_paths && !is_device_ptr(d_paths)) ||
+      !stats) {
+    set_err(ctx, "d_pi, d_traj and d_paths must be device pointers (d_traj, d_paths may be NULL), stats non-NULL");
+    return MDP_E_INVALID;
+  }
+  size_t need = 0;
+  (void)mdp_rollout_query(p, &need);
+  if (!is_device_ptr(scratch) || scratch_bytes < need) {
+    set_err(ctx, "scratch needs %zu device bytes", need);
+    return MDP_E_SCRATCH;
+  }
+  RollParams R;
+  memset(&R, 0, sizeof(R));
+  R.ubar = env->ubar;
+  R.vbar = env->vbar;
+  R.phiu = env->phiu;
+  R.phiv = env->phiv;
+  R.mu = env->mu;
+  R.gbar = env->gbar;
+  R.mask = env->mask;
+  R.pi = d_pi;
+  R.traj = d_traj;
+  mdp_rollout_stats *dstats = (mdp_rollout_stats *)scratch;
+  R.paths = d_paths ? d_paths : (mdp_rollout_path *)((char *)scratch + align_up(sizeof(mdp_rollout_stats)));
+  R.nx = p->nx;
+  R.ny = p->ny;
+  R.nt = p->nt;
+  R.nc = p->nx * p->ny;
+  R.nr = p->n_real;
+  R.K = p->n_modes;
+  R.na = p->n_head * p->n_speed;
+  R.si = p->start_i;
+  R.sj = p->start_j;
+  R.ti = p->target_i;
+  R.tj = p->target_j;
+  R.mean_tstride = p->mean_time_varying ? R.nc : 0;
+  R.mode_tstride = p->mode_time_varying ? (int64_t)p->n_modes * R.nc : 0;
+  R.lam_x = (float)(p->dt / p->dx);
+  R.lam_y = (float)(p->dt / p->dy);
+  R.swept = (p->flags & MDP_FLAG_SWEPT_PATH) ? 1 : 0;
+  R.dt = p->dt;
+  R.r_term = p->r_term;
+  R.r_out = p->r_outbound;
+  R.c_f = p->c_f;
+  R.c_r = p->c_r;
+  action_tables(p, R.tab.hx, R.tab.hy);
+  for (int jf = 0; jf < p->n_speed; ++jf)
+    for (int h = 0; h < p->n_head; ++h) R.speed[jf * p->n_head + h] = p->f_max * (double)(jf + 1) / (double)p->n_speed;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_rollout(R, dstats, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "rollout");
+  if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_rollout_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(ctx, e, "rollout stats copy");
+  return MDP_OK;
+}
+
 }  // extern "C"
 
 // ====================================================================== batches
@@ -1052,6 +1230,7 @@ const char *batch_build_desc(int inst, const mdp_problem *p, const mdp_env *env,
                              std::vector<std::pair<double, BatchItem>> &items)
 {
   if (const char *m = check_env(p, env)) return m;
+  if (p->flags & MDP_FLAG_SWEPT_PATH) return "batches and servers do not take the swept-path test";
   memset(&D, 0, sizeof(D));
   ActionTables T;
   fill_params(p, env, &M, pl, D.P, T);
@@ -1599,14 +1778,15 @@ ReqSizes req_sizes(const mdp_problem *p, const Plan &pl)
   ReqSizes z;
   z.rows = pl.rows;
   z.ns = (int64_t)p->nt * pl.nc;
-  z.cap = pl.rows * (int64_t)std::min(pl.nsg, p->n_real);
+  z.cap = pl.rows * (int64_t)pl.max_row;
   z.keep = align_up(8 * (size_t)(z.rows + 1)) + align_up(4 * (size_t)z.rows) + 2 * align_up(8 * (size_t)z.ns) +
            align_up(4 * (size_t)z.ns) + align_up(sizeof(VIState));
   z.col = align_up(4 * (size_t)z.cap);
   z.cnt = align_up(2 * (size_t)z.cap);
   const size_t items = (size_t)p->nt * max_tiles_per_layer(p);
   z.build = align_up(sizeof(BuildState)) + align_up(sizeof(mdp_build_stats)) + 2 * align_up(4 * (size_t)z.rows) +
-            align_up(4 * items) + 2 * align_up(8 * items) + align_up(8 * (size_t)z.cap);
+            align_up(4 * items) + 2 * align_up(8 * items) + align_up(sizeof(BatchItem) * items) +
+            align_up(8 * (size_t)z.cap);
   return z;
 }
 
@@ -1677,8 +1857,7 @@ struct BuildLane {
   Block blk;                        // its scratch and staging block
   BatchBuildDesc *d_bdesc = nullptr;
   float *d_tabs = nullptr;
-  BatchItem *d_items = nullptr;
-  size_t items_cap = 0;
+  BatchItem *d_items = nullptr;     // the batch's work list, inside its build block
   Pinned h_bdesc, h_items, h_tabs, h_bstat;
   // The batch's build launches are enqueued a few at a time (serve_pump), so
   // that sweeps enqueued meanwhile on other streams reach the GPU between
@@ -1710,6 +1889,8 @@ struct mdp_server {
   std::vector<mdp_served> done;     // completion records not yet polled
   int64_t step_no = 0;
   int64_t n_submitted = 0;
+  double chunk_cost = 0.0;  // work of one build launch (cfg.chunk_cost or the default)
+  double large_cost = 0.0;  // build cost above which a request takes the large lane
   hipEvent_t sync_ev = nullptr;  // end of a step's work on the caller's stream
   // device tables, sized for cfg.max_inflight problems
   BatchVIDesc *d_vrun = nullptr, *d_vret = nullptr;
@@ -1736,7 +1917,7 @@ void serve_free_all(mdp_server *S)
     for (ServeReq *r : L.building) delete r;
     for (hipEvent_t ev : L.ahead)
       if (ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {L.d_bdesc, L.d_tabs, L.d_items};
+    void *bufs[] = {L.d_bdesc, L.d_tabs};
     for (void *p : bufs)
       if (p) (void)hipFree(p);
     if (L.event) (void)hipEventDestroy(L.event);
@@ -1932,6 +2113,10 @@ mdp_status serve_build(mdp_server *S, BuildLane &L, char *blk)
     o += align_up(8 * items_i);
     pool_cap += r->z.cap;
   }
+  size_t n_items_all = 0;
+  for (int i = 0; i < n; ++i) n_items_all += (size_t)fresh[i]->p.nt * fresh[i]->pl.tiles_per_layer;
+  BatchItem *d_items = (BatchItem *)(blk + o);  // room: every request's z.build holds its items
+  o += align_up(sizeof(BatchItem) * n_items_all);
   uint64_t *pool = (uint64_t *)(blk + o);
   std::vector<int> kmax_of(n);
   std::vector<char> near_of(n);
@@ -1954,14 +2139,11 @@ mdp_status serve_build(mdp_server *S, BuildLane &L, char *blk)
   if ((e = plan_build_groups(items, kmax_of, near_of, lds_of, flat, groups, S->cfg.build_share, &cost)) !=
       hipSuccess)
     return hip_fail(S->ctx, e, "serve occupancy");
-  if (flat.size() > L.items_cap) {
-    if (L.d_items) (void)hipFree(L.d_items);
-    L.d_items = nullptr;
-    L.items_cap = 0;
-    if ((e = hipMalloc((void **)&L.d_items, sizeof(BatchItem) * flat.size())) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve items");
-    L.items_cap = flat.size();
+  if (flat.size() != n_items_all) {
+    set_err(S->ctx, "serve work list size");
+    return MDP_E_HIP;
   }
+  L.d_items = d_items;
   if ((e = L.h_items.ensure(sizeof(BatchItem) * flat.size())) != hipSuccess)
     return hip_fail(S->ctx, e, "serve staging");
   memcpy(L.h_items.p, flat.data(), sizeof(BatchItem) * flat.size());
@@ -1973,7 +2155,7 @@ mdp_status serve_build(mdp_server *S, BuildLane &L, char *blk)
     return hip_fail(S->ctx, e, "serve descriptors");
   if ((e = launch_batch_build_init(L.d_bdesc, n, counter, pool_top, s)) != hipSuccess)
     return hip_fail(S->ctx, e, "serve build init");
-  L.plan = plan_build_launches(groups, &cost, kServeChunkCost);
+  L.plan = plan_build_launches(groups, &cost, S->chunk_cost);
   L.next = 0;
   L.ahead_head = L.ahead_n = 0;
   L.tail = false;
@@ -2012,7 +2194,7 @@ void serve_join(mdp_server *S, BuildLane &L)
 }
 
 // Lane of a request: large builds (paper-shaped and above) go to lane 1.
-int lane_of(const ServeReq *r) { return build_cost(r) > kServeLargeCost ? 1 : 0; }
+int lane_of(const mdp_server *S, const ServeReq *r) { return build_cost(r) > S->large_cost ? 1 : 0; }
 
 // Admit queued requests of lane li's size class, in order, into a new build
 // batch while slots and pool space last, and enqueue its build.
@@ -2024,7 +2206,7 @@ mdp_status serve_admit(mdp_server *S, int li)
   for (auto it = S->queue.begin(); it != S->queue.end();) {
     if ((int)(S->running.size() + S->n_building()) >= S->cfg.max_inflight) break;
     ServeReq *r = *it;
-    if (lane_of(r) != li) {
+    if (lane_of(S, r) != li) {
       ++it;
       continue;
     }
@@ -2097,9 +2279,15 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
     set_err(ctx, "the model pool must be device memory");
     return MDP_E_INVALID;
   }
+  if (!(cfg->chunk_cost >= 0.0) || !(cfg->large_cost >= 0.0)) {
+    set_err(ctx, "chunk_cost and large_cost must be >= 0");
+    return MDP_E_INVALID;
+  }
   mdp_server *S = new mdp_server();
   S->ctx = ctx;
   S->cfg = *cfg;
+  S->chunk_cost = cfg->chunk_cost > 0.0 ? cfg->chunk_cost : kServeChunkCost;
+  S->large_cost = cfg->large_cost > 0.0 ? cfg->large_cost : kServeLargeCost;
   S->pool = (char *)pool;
   S->pool_bytes = pool_bytes / kAlign * kAlign;
   S->alloc.reset(S->pool_bytes);
@@ -2143,6 +2331,10 @@ mdp_status mdp_server_submit(mdp_server *S, const mdp_problem *p, const mdp_env 
   if (!S || !p || !env) return MDP_E_INVALID;
   if (mission < 0 || mission > 2) {
     set_err(S->ctx, "mission must be 0, 1 or 2");
+    return MDP_E_INVALID;
+  }
+  if (p->flags & MDP_FLAG_SWEPT_PATH) {
+    set_err(S->ctx, "servers do not take the swept-path test");
     return MDP_E_INVALID;
   }
   ServeReq *r = new ServeReq();

@@ -122,14 +122,14 @@ struct TileOut {
 
 // One tile of cells at layer t, every action of those cells, every realization.
 // POOL: entries go to a bump-allocated pool slot instead of O.stage.
-template <int KMAX, bool PACK16, bool NEAR, bool POOL, typename PT>
+template <int KMAX, bool PACK16, bool NEAR, bool POOL, bool SWEPT = false, typename PT>
 __device__ void build_tile(const PT &P, const int t, const int tile, BuildState *bst,
                            const TileOut &O, uint32_t *lds)
 {
   const int HW = P.hw;                              // words per bin (power of 2)
   const int sstr = 2 * P.rch + 4;                   // floats per staged cell (padded)
-  uint32_t *hist = lds;
-  float *stage = reinterpret_cast<float *>(lds + P.nsg * HW);
+  uint32_t *hist = lds;                             // [nbins][HW]; with SWEPT, bin nsg holds swept-path DEAD
+  float *stage = reinterpret_cast<float *>(lds + P.nbins * HW);
   float *tab = stage + P.cells_per_tile * sstr;     // Hx[kMaxA], Hy[kMaxA]
   uint32_t *red = reinterpret_cast<uint32_t *>(tab + 2 * kMaxA);  // 16 words
 
@@ -155,7 +155,19 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   const bool is_obst = P.mask != nullptr && P.mask[(size_t)t * nc + c] != 0;
   const bool sampled = lane_row && !is_target && !is_obst;
 
-  for (int w = tid; w < P.nsg * HW; w += kBlock) hist[w] = 0u;
+  for (int w = tid; w < P.nbins * HW; w += kBlock) hist[w] = 0u;
+  // Swept-path test: only rows with an obstacle cell at t+1 inside their
+  // sub-grid (other than their own cell) can have a blocked path.
+  bool swept_row = false;
+  const uint8_t *mask1 = (SWEPT && P.mask != nullptr) ? P.mask + (size_t)(t + 1) * nc : nullptr;
+  if (SWEPT && mask1 != nullptr && sampled) {
+    for (int dj = -P.hy; dj <= P.hy; ++dj)
+      for (int di = -P.hx; di <= P.hx; ++di) {
+        const int a2 = ci + di, b2 = cj + dj;
+        if ((di | dj) != 0 && a2 >= 0 && a2 < P.nx && b2 >= 0 && b2 < P.ny && mask1[(size_t)b2 * P.nx + a2] != 0)
+          swept_row = true;
+      }
+  }
 
   // word of bin (iy - cj + hy, ix - ci + hx) = (iy*W + ix)*HW + base
   const int col_l = tid & (HW - 1);
@@ -245,12 +257,16 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
       // the next group is loaded before the current group's counter updates.
       const float4 *st4 = reinterpret_cast<const float4 *>(stage + cl * sstr);
       const int n4 = nloc >> 2;
+      // word of the swept-path DEAD bin (bin nsg) of this lane
+      const int dead4 = (int)__builtin_amdgcn_groupstaticsize() + (P.nsg * HW + col_l) * 4;
       auto bin = [&](float px, float py) {
         const float X = px + hxa;
         const float Y = py + hya;
         const int ix = cvt_floor(X);
         const int iy = cvt_floor(Y);
-        lds_add(mad_i24_s(mad_i24_s(iy, W, ix), HW4, base4), inc);
+        int addr = mad_i24_s(mad_i24_s(iy, W, ix), HW4, base4);
+        if (SWEPT && swept_row && swept_blocked(mask1, P.nx, P.ny, ci, cj, ix, iy, X, Y)) addr = dead4;
+        lds_add(addr, inc);
         if (NEAR)
           near_cnt += ((fabsf(X - rintf(X)) < P.eps_x) || (fabsf(Y - rintf(Y)) < P.eps_y)) ? 1u : 0u;
       };
@@ -344,6 +360,10 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
         }
       }
     }
+    if (SWEPT) {  // samples whose path entered an obstacle at t+1
+      const uint32_t wv = hist[P.nsg * HW + col_l];
+      dead += PACK16 ? ((wv >> shift) & 0xffffu) : wv;
+    }
     nnz += (dead ? 1u : 0u) + (tgt ? 1u : 0u);
   } else if (lane_row) {
     nnz = 1;
@@ -427,7 +447,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   }
 }
 
-template <int KMAX, bool PACK16, bool NEAR>
+template <int KMAX, bool PACK16, bool NEAR, bool SWEPT>
 __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const SlabParams S)
 {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -445,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
   O.pool_top = nullptr;
   O.pool_cap = 0;
   O.base_out = nullptr;
-  build_tile<KMAX, PACK16, NEAR, false>(P, t, tile, S.st, O, lds);
+  build_tile<KMAX, PACK16, NEAR, false, SWEPT>(P, t, tile, S.st, O, lds);
 }
 
 // Action displacement tables into device memory (one thread per entry).
@@ -459,13 +479,13 @@ __global__ void k_fill_tab(const ActionTables T, float *tab)
   if (k < 2 * kMaxA) tab[k] = x;
 }
 
-__global__ void k_build_init(BuildState *st)
+__global__ void k_build_init(BuildState *st, const int64_t *row_ptr_row0)
 {
   if (threadIdx.x == 0) {
     st->n_escape = 0;
     st->n_near = 0;
     st->samples = 0;
-    st->running_nnz = 0;
+    st->running_nnz = row_ptr_row0 ? *row_ptr_row0 : 0;
   }
 }
 
@@ -760,14 +780,20 @@ hipError_t launch_fill_tab(const ActionTables &T, float *tab, hipStream_t s)
 
 hipError_t launch_build_init(BuildState *st, hipStream_t s)
 {
-  hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, s, st, (const int64_t *)nullptr);
   return hipGetLastError();
 }
 
-template <int KMAX, bool PACK16, bool NEAR>
+hipError_t launch_build_init_from(BuildState *st, const int64_t *row_ptr_row0, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, s, st, row_ptr_row0);
+  return hipGetLastError();
+}
+
+template <int KMAX, bool PACK16, bool NEAR, bool SWEPT>
 static hipError_t launch_build_t(const BuildParams &P, const SlabParams &S, size_t lds, hipStream_t s)
 {
-  auto kern = k_build<KMAX, PACK16, NEAR>;
+  auto kern = k_build<KMAX, PACK16, NEAR, SWEPT>;
   static bool attr_set = false;  // raise the dynamic-LDS limit once per instantiation
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -780,28 +806,38 @@ static hipError_t launch_build_t(const BuildParams &P, const SlabParams &S, size
   return hipGetLastError();
 }
 
-template <int KMAX>
+template <int KMAX, bool SWEPT>
 static hipError_t launch_build_k(const BuildParams &P, const SlabParams &S, bool pack16, bool near,
                                  size_t lds, hipStream_t s)
 {
   if (pack16)
-    return near ? launch_build_t<KMAX, true, true>(P, S, lds, s) : launch_build_t<KMAX, true, false>(P, S, lds, s);
-  return near ? launch_build_t<KMAX, false, true>(P, S, lds, s) : launch_build_t<KMAX, false, false>(P, S, lds, s);
+    return near ? launch_build_t<KMAX, true, true, SWEPT>(P, S, lds, s)
+                : launch_build_t<KMAX, true, false, SWEPT>(P, S, lds, s);
+  return near ? launch_build_t<KMAX, false, true, SWEPT>(P, S, lds, s)
+              : launch_build_t<KMAX, false, false, SWEPT>(P, S, lds, s);
+}
+
+template <bool SWEPT>
+static hipError_t launch_build_sw(const BuildParams &P, const SlabParams &S, int kmax, bool pack16, bool near,
+                                  size_t lds, hipStream_t s)
+{
+  switch (kmax) {
+    case 2: return launch_build_k<2, SWEPT>(P, S, pack16, near, lds, s);
+    case 4: return launch_build_k<4, SWEPT>(P, S, pack16, near, lds, s);
+    case 6: return launch_build_k<6, SWEPT>(P, S, pack16, near, lds, s);
+    case 8: return launch_build_k<8, SWEPT>(P, S, pack16, near, lds, s);
+    case 10: return launch_build_k<10, SWEPT>(P, S, pack16, near, lds, s);
+    case 12: return launch_build_k<12, SWEPT>(P, S, pack16, near, lds, s);
+    case 14: return launch_build_k<14, SWEPT>(P, S, pack16, near, lds, s);
+    default: return launch_build_k<16, SWEPT>(P, S, pack16, near, lds, s);
+  }
 }
 
 hipError_t launch_build_slab(const BuildParams &P, const SlabParams &S, int kmax, bool pack16, bool near,
-                             size_t lds, hipStream_t s)
+                             bool swept, size_t lds, hipStream_t s)
 {
-  switch (kmax) {
-    case 2: return launch_build_k<2>(P, S, pack16, near, lds, s);
-    case 4: return launch_build_k<4>(P, S, pack16, near, lds, s);
-    case 6: return launch_build_k<6>(P, S, pack16, near, lds, s);
-    case 8: return launch_build_k<8>(P, S, pack16, near, lds, s);
-    case 10: return launch_build_k<10>(P, S, pack16, near, lds, s);
-    case 12: return launch_build_k<12>(P, S, pack16, near, lds, s);
-    case 14: return launch_build_k<14>(P, S, pack16, near, lds, s);
-    default: return launch_build_k<16>(P, S, pack16, near, lds, s);
-  }
+  return swept ? launch_build_sw<true>(P, S, kmax, pack16, near, lds, s)
+               : launch_build_sw<false>(P, S, kmax, pack16, near, lds, s);
 }
 
 hipError_t launch_batch_build_init(BatchBuildDesc *D, int n, unsigned int *counter,

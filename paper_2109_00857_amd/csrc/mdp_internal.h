@@ -29,6 +29,7 @@ struct BuildParams {
   int64_t rows;
   int nx, ny, nt, nc, na, nr, K;
   int hx, hy, W, nsg;
+  int nbins;                // histogram bins: nsg, plus the swept-path DEAD bin
   int ti, tj;               // target cell
   int mean_tstride;         // nc if the mean varies in time, else 0 (elements)
   int64_t mode_tstride;     // K*nc if the modes vary in time, else 0
@@ -94,6 +95,38 @@ struct BatchItem {
   int inst, t, tile, pad;
 };
 
+// Swept-path obstacle test (MDP_FLAG_SWEPT_PATH): does the straight step from
+// the centre of cell (ci, cj) to the landing point (X, Y), in cell units,
+// enter an obstacle cell of mask layer `m1` (the layer at t+1) other than the
+// source cell? Each candidate cell of the segment's bounding box is tested
+// against the open unit square by separating axes (x, y, the segment's
+// normal); with fp32 landing coordinates every difference and product is exact
+// in fp64, so the outcome is exact.
+__device__ inline bool segment_meets_cell(double x0, double y0, double x1, double y1, int a, int b)
+{
+  const double lx = fmin(x0, x1), hx = fmax(x0, x1), ly = fmin(y0, y1), hy = fmax(y0, y1);
+  if (!(lx < (double)a + 1.0 && hx > (double)a && ly < (double)b + 1.0 && hy > (double)b)) return false;
+  const double dx = x1 - x0, dy = y1 - y0;
+  const double f00 = dx * ((double)b - y0) - dy * ((double)a - x0);
+  const double f10 = dx * ((double)b - y0) - dy * ((double)(a + 1) - x0);
+  const double f01 = dx * ((double)(b + 1) - y0) - dy * ((double)a - x0);
+  const double f11 = dx * ((double)(b + 1) - y0) - dy * ((double)(a + 1) - x0);
+  return fmin(fmin(f00, f10), fmin(f01, f11)) < 0.0 && fmax(fmax(f00, f10), fmax(f01, f11)) > 0.0;
+}
+
+__device__ inline bool swept_blocked(const uint8_t *m1, int nx, int ny, int ci, int cj, int ix, int iy, float X,
+                                     float Y)
+{
+  const double x0 = (double)ci + 0.5, y0 = (double)cj + 0.5, x1 = (double)X, y1 = (double)Y;
+  const int a0 = max(min(ci, ix), 0), a1 = min(max(ci, ix), nx - 1);
+  const int b0 = max(min(cj, iy), 0), b1 = min(max(cj, iy), ny - 1);
+  bool hit = false;
+  for (int b = b0; b <= b1; ++b)
+    for (int a = a0; a <= a1; ++a)
+      if (!(a == ci && b == cj) && m1[(size_t)b * nx + a] != 0 && segment_meets_cell(x0, y0, x1, y1, a, b)) hit = true;
+  return hit;
+}
+
 // Copy of an entry of a device table that no kernel writes while it is read,
 // fetched through the constant address space: at a wave-uniform address the
 // words arrive by scalar loads instead of occupying vector registers.
@@ -113,8 +146,11 @@ __device__ inline T load_const(const T *p)
 // Launchers (return hipError_t of the launch)
 hipError_t launch_fill_tab(const ActionTables &T, float *tab, hipStream_t s);
 hipError_t launch_build_init(BuildState *st, hipStream_t s);
+// Build bookkeeping for a rebuild of the layers from row `row0` on: entries
+// before it are kept, so the running entry count starts at row_ptr[row0].
+hipError_t launch_build_init_from(BuildState *st, const int64_t *row_ptr_row0, hipStream_t s);
 hipError_t launch_build_slab(const BuildParams &P, const SlabParams &S, int kmax, bool pack16,
-                             bool near, size_t lds_bytes, hipStream_t s);
+                             bool near, bool swept, size_t lds_bytes, hipStream_t s);
 hipError_t launch_scan_wg(const SlabParams &S, int n_wg, int64_t *row_ptr_end, hipStream_t s);
 hipError_t launch_copy(const BuildParams &P, const SlabParams &S, const ModelOut &M, int n_wg,
                        hipStream_t s);
@@ -158,7 +194,7 @@ struct VIParams {
   int win_rows;             // grid rows of the staged window of v(t + 1); 0: gather from memory
   int max_row;              // most entries a row can hold, min(N_sg, n_real)
   int n_wg;                 // launched workgroups
-  int pad;
+  int t_lo;                 // first layer a sweep recomputes (0 but for mdp_value_iterate_layers)
   double inv_nr, tol;
   VIState *st;
 };
@@ -237,5 +273,25 @@ hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *blo
 hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, mdp_vi_stats *dev_stats,
                             hipStream_t s);
 hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s);
+
+// Policy rollouts (rollout.hip): one lane per realization.
+struct RollParams {
+  const float *ubar, *vbar, *phiu, *phiv, *mu, *gbar;
+  const uint8_t *mask;
+  const int32_t *pi;        // [nt][ny][nx]
+  int32_t *traj;            // [nt + 1][n_real] or nullptr
+  mdp_rollout_path *paths;  // [n_real]
+  int nx, ny, nt, nc, nr, K, na;
+  int si, sj, ti, tj;
+  int mean_tstride;         // elements
+  int64_t mode_tstride;     // elements
+  float lam_x, lam_y;
+  int swept;                // MDP_FLAG_SWEPT_PATH
+  double dt, r_term, r_out, c_f, c_r;
+  ActionTables tab;         // Hx, Hy in cell units per step
+  double speed[kMaxA];      // F of each action
+};
+
+hipError_t launch_rollout(const RollParams &P, mdp_rollout_stats *dev_stats, hipStream_t s);
 
 }  // namespace mdpk

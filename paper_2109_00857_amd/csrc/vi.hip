@@ -254,10 +254,12 @@ template <typename F>
 __device__ inline void for_blocks(const VIParams &P, int t_hi, F &&body)
 {
   const int bpl = P.blocks_per_layer;
-  const int nb = t_hi * bpl;  // < 2^31: the state count fits 32 bits
+  const int t_lo = min(P.t_lo, t_hi);      // layers [t_lo, t_hi)
+  const int b0 = t_lo * bpl;
+  const int nb = (t_hi - t_lo) * bpl;      // < 2^31: the state count fits 32 bits
   const int x = (int)blockIdx.x % kXcds, nslot = (int)gridDim.x / kXcds;
-  const int b_end = (int)((int64_t)nb * (x + 1) / kXcds);
-  int b = (int)((int64_t)nb * x / kXcds) + (int)blockIdx.x / kXcds;
+  const int b_end = b0 + (int)((int64_t)nb * (x + 1) / kXcds);
+  int b = b0 + (int)((int64_t)nb * x / kXcds) + (int)blockIdx.x / kXcds;
   if (b >= b_end) return;
   const int gq = nslot / bpl, gr = nslot % bpl;
   int t = b / bpl, c = b - t * bpl;
@@ -348,13 +350,15 @@ __global__ void k_vi_init(VIState *st, int n)
 }
 
 // After the sweeps: the result sits in v after an even number of sweeps and in
-// v_alt after an odd number; bring it back into v and publish the stats.
+// v_alt after an odd number; bring it back into v (the states of the layers the
+// sweeps recomputed, t >= P.t_lo) and publish the stats.
 __global__ __launch_bounds__(kBlock) void k_vi_finish(const VIParams P, double *v, const double *v_alt,
                                                        mdp_vi_stats *out)
 {
   const int sweeps = P.st->sweeps;
   if (sweeps & 1) {
-    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < P.ns; s += (int64_t)gridDim.x * kBlock)
+    const int64_t s0 = (int64_t)P.t_lo * P.nc;
+    for (int64_t s = s0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; s < P.ns; s += (int64_t)gridDim.x * kBlock)
       v[s] = v_alt[s];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -812,7 +816,7 @@ hipError_t launch_vi_sweep(const VIParams &P, const double *vin, double *vout, i
   static bool attr = false;
   hipError_t e = allow_lds((const void *)k_vi_sweep, attr);
   if (e != hipSuccess) return e;
-  const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
+  const int64_t nb = (int64_t)std::max(t_hi - P.t_lo, 0) * P.blocks_per_layer;
   const int grid = vi_grid(nb, std::min(P.n_wg, kViGridMax));
   hipLaunchKernelGGL(k_vi_sweep, dim3(grid), dim3(kBlock), single_lds(P), s, P, vin, vout, t_hi, wg_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -24,6 +24,7 @@ MDP_E_HIP = 4
 MDP_E_NOT_CONVERGED = 5
 MDP_E_SCRATCH = 6
 MDP_FLAG_NEAR_EDGE = 1
+MDP_FLAG_SWEPT_PATH = 2
 MISSION_TIME, MISSION_ENERGY, MISSION_NET_ENERGY = 0, 1, 2
 
 
@@ -84,9 +85,26 @@ class MdpTuneReport(C.Structure):
                 ("pack16", C.c_int32 * MDP_MAX_TUNE), ("ms", C.c_double * MDP_MAX_TUNE)]
 
 
+MDP_ROLL_ARRIVED, MDP_ROLL_OUTBOUND, MDP_ROLL_OBSTACLE, MDP_ROLL_HORIZON = 0, 1, 2, 3
+
+
+class MdpRolloutPath(C.Structure):
+    _fields_ = [("outcome", C.c_int32), ("steps", C.c_int32), ("ret", C.c_double * 3), ("energy", C.c_double),
+                ("fsum", C.c_double)]
+
+
+class MdpRolloutStats(C.Structure):
+    _fields_ = [("n_real", C.c_int64), ("n_arrived", C.c_int64), ("n_outbound", C.c_int64),
+                ("n_obstacle", C.c_int64), ("n_horizon", C.c_int64), ("p_reach", C.c_double),
+                ("mean_time_arrived", C.c_double), ("mean_energy_arrived", C.c_double),
+                ("mean_net_energy_arrived", C.c_double), ("mean_speed_arrived", C.c_double),
+                ("mean_return", C.c_double * 3)]
+
+
 class MdpServerConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("sweeps_per_step", C.c_int32), ("max_sweeps", C.c_int32),
-                ("build_share", C.c_int32), ("tol", C.c_double)]
+                ("build_share", C.c_int32), ("tol", C.c_double), ("chunk_cost", C.c_double),
+                ("large_cost", C.c_double)]
 
 
 class MdpServed(C.Structure):
@@ -117,12 +135,19 @@ def load():
             "mdp_subgrid_auto": ([vp, P, C.POINTER(MdpEnv), C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp],
                                  C.c_int32),
             "mdp_build": ([vp, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), vp, C.c_size_t, vp, vp], C.c_int32),
+            "mdp_build_sync": ([vp, vp, vp], C.c_int32),
+            "mdp_build_from": ([vp, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), C.c_int32, vp, C.c_size_t, vp, vp],
+                               C.c_int32),
+            "mdp_value_iterate_layers": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_int32, C.c_double, C.c_int32, vp,
+                                          vp, C.c_size_t, vp, vp], C.c_int32),
             "mdp_value_iterate": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp,
                                    C.c_size_t, vp, vp], C.c_int32),
             "mdp_value_iterate_missions": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.POINTER(C.c_int32),
                                             C.c_double, C.c_int32, C.POINTER(vp), vp, C.c_size_t, vp, vp],
                                            C.c_int32),
             "mdp_policy": ([vp, P, C.POINTER(MdpModel), C.c_int32, vp, vp, vp], C.c_int32),
+            "mdp_rollout_query": ([P, C.POINTER(C.c_size_t)], C.c_int32),
+            "mdp_rollout": ([vp, P, C.POINTER(MdpEnv), vp, vp, vp, vp, C.c_size_t, vp, vp], C.c_int32),
             "mdp_batch_query": ([C.c_int32, P, C.c_int64, C.POINTER(C.c_size_t)], C.c_int32),
             "mdp_batch_create": ([vp, C.c_int32, P, C.POINTER(MdpEnv), C.POINTER(MdpModel), vp, vp, vp, C.c_int64,
                                   vp, C.c_size_t, C.POINTER(vp)], C.c_int32),
@@ -154,7 +179,9 @@ def load():
 
 
 EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_error", "mdp_build_query",
-            "mdp_subgrid_auto", "mdp_build", "mdp_value_iterate", "mdp_value_iterate_missions", "mdp_policy",
+            "mdp_subgrid_auto", "mdp_build", "mdp_build_sync", "mdp_build_from", "mdp_value_iterate",
+            "mdp_value_iterate_layers", "mdp_value_iterate_missions",
+            "mdp_policy", "mdp_rollout_query", "mdp_rollout",
             "mdp_ctx_profile",
             "mdp_ctx_profile_read", "mdp_batch_query", "mdp_batch_create", "mdp_batch_build", "mdp_batch_solve",
             "mdp_batch_stats", "mdp_batch_capture", "mdp_batch_replay", "mdp_batch_destroy",
@@ -232,6 +259,37 @@ def mdp_build(ctx, problem: dict, env: dict, model: dict, scratch: torch.Tensor,
     _check(ctx, rc, "mdp_build")
 
 
+def mdp_build_from(ctx, problem: dict, env: dict, model: dict, t0: int, scratch: torch.Tensor, stats: torch.Tensor,
+                   stream=None) -> None:
+    """Enqueue the rebuild of layers [t0, nt) of a built model after the environment changed."""
+    e = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    rc = load().mdp_build_from(ctx, C.byref(problem_struct(problem)), C.byref(e), C.byref(m), t0, _ptr(scratch),
+                               scratch.numel(), stats.data_ptr(), _stream_handle(stream))
+    _check(ctx, rc, "mdp_build_from")
+
+
+def mdp_value_iterate_layers(ctx, problem: dict, model: dict, mission: int, t_first: int, tol: float,
+                             max_sweeps: int, v: torch.Tensor, scratch: torch.Tensor, stats: torch.Tensor,
+                             stream=None) -> None:
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    rc = load().mdp_value_iterate_layers(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, t_first, tol,
+                                         max_sweeps, _ptr(v), _ptr(scratch), scratch.numel(), stats.data_ptr(),
+                                         _stream_handle(stream))
+    _check(ctx, rc, "mdp_value_iterate_layers")
+
+
+def mdp_build_sync(ctx, stats: torch.Tensor, stream=None) -> int:
+    """Wait for the build on `stream`; return its device status (MDP_OK, MDP_E_CAPACITY,
+    MDP_E_SUBGRID) without raising for those two."""
+    rc = load().mdp_build_sync(ctx, stats.data_ptr(), _stream_handle(stream))
+    if rc not in (MDP_OK, MDP_E_CAPACITY, MDP_E_SUBGRID):
+        _check(ctx, rc, "mdp_build_sync")
+    return rc
+
+
 def mdp_value_iterate(ctx, problem: dict, model: dict, mission: int, tol: float, max_sweeps: int,
                       v: torch.Tensor, scratch: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
     m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
@@ -263,6 +321,31 @@ def mdp_policy(ctx, problem: dict, model: dict, mission: int, v: torch.Tensor, p
     rc = load().mdp_policy(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, _ptr(v), _ptr(pi),
                            _stream_handle(stream))
     _check(ctx, rc, "mdp_policy")
+
+
+def mdp_rollout_query(problem: dict) -> int:
+    n = C.c_size_t()
+    rc = load().mdp_rollout_query(C.byref(problem_struct(problem)), C.byref(n))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_rollout_query: invalid problem")
+    return n.value
+
+
+def mdp_rollout(ctx, problem: dict, env: dict, pi: torch.Tensor, traj, paths, scratch: torch.Tensor,
+                stats: torch.Tensor, stream=None) -> None:
+    """Enqueue the rollout of policy `pi`; `stats` is a (pinned) uint8 host tensor of
+    sizeof(mdp_rollout_stats); traj (int32 [nt+1][n_real]) and paths may be None."""
+    e = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
+    rc = load().mdp_rollout(ctx, C.byref(problem_struct(problem)), C.byref(e), _ptr(pi), _ptr(traj), _ptr(paths),
+                            _ptr(scratch), scratch.numel(), stats.data_ptr(), _stream_handle(stream))
+    _check(ctx, rc, "mdp_rollout")
+
+
+def rollout_stats_dict(buf: torch.Tensor) -> dict:
+    s = MdpRolloutStats.from_buffer_copy(bytes(buf.numpy()))
+    out = {k: getattr(s, k) for k, _ in MdpRolloutStats._fields_}
+    out["mean_return"] = list(s.mean_return)
+    return out
 
 
 def mdp_ctx_profile(ctx, enable: bool) -> None:
@@ -337,7 +420,7 @@ class Planner:
             model = self.alloc_model(problem, capacity)
             st = stats_buffer(MdpBuildStats)
             mdp_build(self.ctx, problem, env, model, scratch, st, stream)
-            (stream or torch.cuda.current_stream()).synchronize()
+            mdp_build_sync(self.ctx, st, stream)
             stats = read_stats(st, MdpBuildStats)
             if stats["status"] != MDP_E_CAPACITY:
                 break
@@ -381,6 +464,21 @@ class Planner:
         pi = torch.empty(ns, dtype=torch.int32, device=self.device)
         mdp_policy(self.ctx, problem, model, mission, v, pi, stream)
         return pi
+
+    def rollout(self, problem: dict, env: dict, pi: torch.Tensor, keep_traj: bool = True, stream=None):
+        """Roll pi out in every realization. Returns (traj [nt+1][n_real] or None,
+        paths as a dict of numpy arrays, stats dict); synchronises the stream."""
+        nr, nt = problem["n_real"], problem["nt"]
+        traj = torch.empty((nt + 1, nr), dtype=torch.int32, device=self.device) if keep_traj else None
+        paths = torch.empty(nr * C.sizeof(MdpRolloutPath), dtype=torch.uint8, device=self.device)
+        scratch = torch.empty(mdp_rollout_query(problem), dtype=torch.uint8, device=self.device)
+        st = stats_buffer(MdpRolloutStats)
+        mdp_rollout(self.ctx, problem, env, pi, traj, paths, scratch, st, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        raw = np.frombuffer(paths.cpu().numpy().tobytes(), dtype=np.dtype(
+            [("outcome", "<i4"), ("steps", "<i4"), ("ret", "<f8", (3,)), ("energy", "<f8"), ("fsum", "<f8")]))
+        pd = {k: np.ascontiguousarray(raw[k]) for k in ("outcome", "steps", "ret", "energy", "fsum")}
+        return traj, pd, rollout_stats_dict(st)
 
 
 # ---------------------------------------------------------------- batches
@@ -502,11 +600,12 @@ class Server:
     tensors owned here until its completion is polled."""
 
     def __init__(self, planner: "Planner", pool_bytes: int, max_inflight: int = 64, sweeps_per_step: int = 8,
-                 tol: float = 1e-6, max_sweeps: int = 100000, stream=None, build_share: int = 100):
+                 tol: float = 1e-6, max_sweeps: int = 100000, stream=None, build_share: int = 100,
+                 chunk_cost: float = 0.0, large_cost: float = 0.0):
         self.pl = planner
         self.h = None
         self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=planner.device)
-        cfg = MdpServerConfig(max_inflight, sweeps_per_step, max_sweeps, build_share, tol)
+        cfg = MdpServerConfig(max_inflight, sweeps_per_step, max_sweeps, build_share, tol, chunk_cost, large_cost)
         h = C.c_void_p()
         _check(planner.ctx, load().mdp_server_create(planner.ctx, C.byref(cfg), self.pool.data_ptr(),
                                                       self.pool.numel(), C.byref(h)), "mdp_server_create")

@@ -61,3 +61,25 @@ def assert_policy_optimal(ora, w, om: dict, mission: int, v_ora, w_ora, pi_gpu) 
     assert not bad.any(), (np.flatnonzero(bad)[:10], qg[bad][:5], qmax[bad][:5])
     _, pi_ora, _ = ora.backward(w, om, mission)
     return float((pi_ora == pi_gpu).mean())
+
+
+def assert_matches_oracle(ora, w, missions, g: dict, stats: dict, values: dict, policies: dict,
+                          om: dict | None = None) -> dict:
+    """Whole-model parity of one problem's GPU outputs against the oracle:
+    counts bit-exact, rewards within tolerance, and for each solved mission the
+    values within tolerance and the policy optimal within it.
+    g: model_to_host(...) of the GPU model (reward slots in ascending mission
+    order of w's mission mask); values / policies: mission -> numpy array."""
+    if om is None:
+        om = ora.build_model(w)
+    assert stats["nnz"] == om["nnz"], (stats["nnz"], om["nnz"])
+    assert stats["n_escape"] == om["n_escape"] == 0
+    if stats.get("n_near_edge", -1) >= 0:
+        assert stats["n_near_edge"] == om["n_near_edge"]
+    assert_counts_equal(g, om)
+    assert_rewards_close(g, om, w.missions())
+    for m in missions:
+        v_ora, _, w_ora = ora.backward(w, om, m)
+        assert_values_close(values[m], v_ora, w_ora)
+        assert_policy_optimal(ora, w, om, m, v_ora, w_ora, policies[m])
+    return om

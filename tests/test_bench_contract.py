@@ -13,19 +13,20 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_measured_traffic_matches_the_kernel_sources():
-    """Each recorded HBM traffic figure names the source it was measured on; a
+def test_measured_counters_match_the_kernel_sources():
+    """Each recorded counter figure names the kernel source it was measured on; a
     stale figure is reported null rather than attributed to changed code."""
     sys.path.insert(0, ROOT)
     import hashlib
 
     import bench
 
-    for kernel, m in bench.MEASURED_TRAFFIC.items():
+    for (kernel, workload), m in bench.MEASURED.items():
         with open(os.path.join(ROOT, m["src"]), "rb") as f:
             current = hashlib.sha256(f.read()).hexdigest()[:16]
-        got = bench.measured_traffic(kernel)
-        if current == m["sha256"]:
-            assert got == m["read"] + m["write"] and got > 0, kernel
-        else:
-            assert got is None, kernel
+        for field in ("read", "write", "valu_insts"):
+            got = bench.measured(kernel, workload, field)
+            if current == m["sha256"] and m.get(field) is not None:
+                assert got == m[field] and got > 0, (kernel, workload, field)
+            else:
+                assert got is None, (kernel, workload, field)

@@ -6,6 +6,8 @@ import pytest
 
 from paper_2109_00857_amd import workloads as W
 
+from gpu_helpers import assert_matches_oracle, model_to_host
+
 pytestmark = pytest.mark.gpu
 
 
@@ -49,6 +51,16 @@ def _same(a, b):
     return a.contiguous().view(-1).cpu().numpy().tobytes() == b.contiguous().view(-1).cpu().numpy().tobytes()
 
 
+def _check_against_oracle(ora, ws, missions, batch, bstats):
+    """Every problem of the batch against the CPU oracle (not only the plain path)."""
+    for i, (w, m) in enumerate(zip(ws, missions)):
+        print(f"[batch] oracle check of problem {i}: {w.problem['nx']}x{w.problem['ny']}x{w.problem['nt']}",
+              flush=True)
+        g = model_to_host(batch.models[i], bstats[i])
+        assert_matches_oracle(ora, w, [m], g, bstats[i], {m: batch.v[i].cpu().numpy()},
+                              {m: batch.pi[i].cpu().numpy()})
+
+
 def _check_against_plain(planner, ws, missions, batch, bstats, vstats):
     for i, (w, m) in enumerate(zip(ws, missions)):
         model, stats, v, vst, pi = _plain(planner, w, m)
@@ -66,7 +78,7 @@ def _check_against_plain(planner, ws, missions, batch, bstats, vstats):
         assert _same(batch.pi[i], pi), i
 
 
-def test_batch_equals_plain(planner):
+def test_batch_equals_plain(planner, ora):
     from paper_2109_00857_amd import mdp
 
     ws = _uneven_problems()
@@ -81,6 +93,7 @@ def test_batch_equals_plain(planner):
     torch.cuda.synchronize()
     bstats, vstats = b.stats()
     _check_against_plain(planner, ws, missions, b, bstats, vstats)
+    _check_against_oracle(ora, ws, missions, b, bstats)
     b.close()
 
 
@@ -150,4 +163,75 @@ def test_batch_graph_replays(planner):
                 assert _same(b.models[i][k][:nnz[i]], ref_models[i][k][:nnz[i]]), (rep, i, k)
             assert _same(b.v[i], ref_v[i]), (rep, i)
             assert _same(b.pi[i], ref_pi[i]), (rep, i)
+    b.close()
+
+
+def _sampled_rows_and_bellman(ora, w, m, model, v, pi, rng, n_rows=12, n_states=4):
+    """Sampled rows bit-exact against the oracle's rows, and at sampled states one
+    Bellman step with the oracle's rows and the GPU's next-layer values gives the
+    GPU's value, the GPU's action attaining the maximum (both within 1e-5 of the
+    state's absolute scale)."""
+    import torch
+
+    p = w.problem
+    nc, na, ns, nr = p["nx"] * p["ny"], w.n_actions, w.n_states, p["n_real"]
+    rows = np.sort(rng.choice(w.n_rows, n_rows, replace=False))
+    rp = model["row_ptr"][torch.as_tensor(np.concatenate([rows, rows + 1]), device=model["row_ptr"].device)]
+    rp = rp.cpu().numpy()
+    R = model["reward"][0, torch.as_tensor(rows, device=model["reward"].device)].cpu().numpy().astype(np.float64)
+    for k, row in enumerate(rows):
+        s, a = divmod(int(row), na)
+        t, c = divmod(s, nc)
+        cols, cnts, Ro, Ao, ne, _ = ora.row(w, t, c, a)
+        assert ne == 0
+        lo, hi = rp[k], rp[len(rows) + k]
+        np.testing.assert_array_equal(model["col"][lo:hi].cpu().numpy(), cols, err_msg=f"row {row}")
+        np.testing.assert_array_equal(model["cnt"][lo:hi].cpu().numpy().astype(np.int32), cnts, err_msg=f"row {row}")
+        assert abs(R[k] - Ro[m]) <= 1e-5 * Ao[m], (row, R[k], Ro[m], Ao[m])
+    for s in rng.choice(ns, n_states, replace=False):
+        t, c = divmod(int(s), nc)
+        q = np.zeros(na)
+        scale = 0.0
+        for a in range(na):
+            cols, cnts, Ro, Ao, _, _ = ora.row(w, t, c, a)
+            tr = cols < ns
+            q[a] = Ro[m] + float((cnts[tr] * v[cols[tr]]).sum()) / nr
+            scale = max(scale, Ao[m] + float((cnts[tr] * np.abs(v[cols[tr]])).sum()) / nr)
+        assert abs(v[s] - q.max()) <= 1e-5 * scale, (int(s), v[s], q.max(), scale)
+        assert q[pi[s]] >= q.max() - 1e-5 * scale, (int(s), pi[s], q[pi[s]], q.max())
+
+
+def test_batched_mix_against_oracle(planner, ora):
+    """The 64-instance uneven batch as benchmarked (sub-grids sized on the device,
+    one persistent build per kernel group, one sweep launch per iteration): the
+    four smallest instances whole against the oracle; every instance on sampled
+    rows (bit-exact counts) and on the Bellman identity at sampled states."""
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    ws = [W.batched_instance(i) for i in range(64)]
+    envs = [planner.upload_env(w) for w in ws]
+    for w, env in zip(ws, envs):
+        w.problem["sub_hx"], w.problem["sub_hy"] = mdp.mdp_subgrid_auto(planner.ctx, w.problem, env)
+    missions = [w.missions()[0] for w in ws]
+    print(f"[batch] 64-instance mix: {sum(w.nominal_samples for w in ws):.3e} samples", flush=True)
+    b = mdp.Batch(planner, [w.problem for w in ws], envs, missions)
+    bstats = b.build_checked()
+    assert all(s["status"] == 0 for s in bstats), bstats
+    b.solve()
+    torch.cuda.synchronize()
+    bstats, vstats = b.stats()
+    assert all(s["status"] == 0 for s in vstats), vstats
+    order = np.argsort([w.nominal_samples for w in ws])
+    for i in order[:4]:
+        i = int(i)
+        w, m = ws[i], missions[i]
+        print(f"[batch] instance {i} whole against the oracle ({w.nominal_samples:.2e} samples)", flush=True)
+        g = model_to_host(b.models[i], bstats[i])
+        assert_matches_oracle(ora, w, [m], g, bstats[i], {m: b.v[i].cpu().numpy()}, {m: b.pi[i].cpu().numpy()})
+    rng = np.random.default_rng(77)
+    for i, (w, m) in enumerate(zip(ws, missions)):
+        _sampled_rows_and_bellman(ora, w, m, b.models[i], b.v[i].cpu().numpy(), b.pi[i].cpu().numpy(), rng)
+    print("[batch] 64 instances: sampled rows and states match the oracle", flush=True)
     b.close()

@@ -109,3 +109,12 @@ def test_full_size_sampled(planner, ora, which):
             if scale > 0:
                 worst = max(worst, abs(v[s] - q.max()) / scale)
         print(f"[full] {which} mission {m}: sweeps={vst['sweeps']} worst rel Bellman gap={worst:.2e}", flush=True)
+        # the GPU policy rolled out in every realization, on the GPU and in the oracle
+        traj, paths, rst = planner.rollout(p, env, torch.from_numpy(pi).to(planner.device))
+        ro = ora.rollout(w, pi)
+        np.testing.assert_array_equal(traj.cpu().numpy().T, ro["traj"])
+        np.testing.assert_array_equal(paths["outcome"], ro["outcome"])
+        assert np.allclose(paths["ret"], ro["ret"], rtol=1e-12, atol=1e-9)
+        assert rst["n_arrived"] == ro["n_arrived"]
+        print(f"[full] {which} mission {m}: rollouts P(reach)={rst['p_reach']:.4f} "
+              f"E[time|arrived]={rst['mean_time_arrived']:.4g}", flush=True)

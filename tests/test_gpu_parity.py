@@ -286,3 +286,48 @@ def test_vi_missions_rejects_bad_arguments(planner):
     assert e.value.status == mdp.MDP_E_SCRATCH
     vs2, sts = planner.value_iterate_missions(w.problem, model, [1, 0])
     assert all(s["status"] == 0 for s in sts)
+
+
+def test_paper_action_set_two_speeds(planner, ora):
+    """The paper's application action set, 16 headings x 2 speeds, on config-2
+    shapes with all three missions (ragged grid): full parity."""
+    w = W.config2(nx=33, ny=27, nt=5, n_real=800, n_head=16)
+    w.problem["n_speed"] = 2
+    assert w.n_actions == 32
+    _full_parity(planner, ora, w, "16 headings x 2 speeds")
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_two_speed_corridor(planner, ora, case):
+    """The hand-derived two-speed corridor (slow when the horizon allows, fast
+    when it must) on the GPU: its values and start actions."""
+    with open(os.path.join(GOLDEN, "two_speed_corridor.json")) as f:
+        g = json.load(f)
+    s, c = g["setup"], g["cases"][case]
+    w = W.uniform_flow(s["nx"], s["ny"], c["nt"], s["u0"], s["v0"], n_real=8, n_head=s["n_head"], f_max=s["f_max"],
+                       dx=s["dx"], dy=s["dy"], dt=s["dt"], start=tuple(s["start"]), target=tuple(s["target"]),
+                       sub_h=2, n_speed=s["n_speed"], mission_mask=3)
+    p, env, model, stats, om = _full_parity(planner, ora, w, f"two-speed corridor case {case}")
+    v, _ = planner.value_iterate(p, model, c["mission"])
+    pi = planner.policy(p, model, c["mission"], v).cpu().numpy()
+    s0 = s["start"][1] * s["nx"] + s["start"][0]
+    assert abs(float(v[s0]) - c["v_start"]) < 1e-12 and pi[s0] == c["pi_start"]
+
+
+def test_swept_path_obstacles(planner, ora):
+    """The swept-path obstacle test (MDP_FLAG_SWEPT_PATH) with moving discs, two
+    speeds and long steps, against the oracle: full parity, and some samples do
+    move to DEAD compared with the landing-cell test alone."""
+    from paper_2109_00857_amd import mdp
+
+    w = W.config2(nx=30, ny=26, nt=4, n_real=500, K=4, n_head=8)
+    w.problem.update(n_speed=2, f_max=0.9, sub_hx=4, sub_hy=4)
+    om_plain = ora.build_model(w)
+    w.problem["flags"] |= mdp.MDP_FLAG_SWEPT_PATH
+    p, env, model, stats, om = _full_parity(planner, ora, w, "swept path")
+    ns = w.n_states
+    dead_plain = int(om_plain["cnt"][om_plain["col"] == ns].sum())
+    dead_swept = int(om["cnt"][om["col"] == ns].sum())
+    assert dead_swept > dead_plain, (dead_swept, dead_plain)
+    with pytest.raises(mdp.MdpError):
+        mdp.Batch(planner, [p], [env], [0])

@@ -4,6 +4,8 @@ import pytest
 
 from paper_2109_00857_amd import workloads as W
 
+from gpu_helpers import assert_policy_optimal, assert_values_close
+
 pytestmark = pytest.mark.gpu
 
 
@@ -62,6 +64,19 @@ def _run(srv, reqs, envs, per_step=2):
     return done
 
 
+def _check_oracle(ora, reqs, done):
+    """Every served request's values and policy against the CPU oracle."""
+    for tag, (w, m) in enumerate(reqs):
+        rec = done[tag]
+        w1 = W.Workload(w.name, dict(w.problem, mission_mask=1 << m), w.ubar, w.vbar, w.phiu, w.phiv, w.mu,
+                        w.gbar, w.mask)
+        om = ora.build_model(w1)
+        assert rec["nnz"] == om["nnz"], (tag, rec["nnz"], om["nnz"])
+        v_ora, _, w_ora = ora.backward(w1, om, m)
+        assert_values_close(rec["v"].numpy(), v_ora, w_ora)
+        assert_policy_optimal(ora, w1, om, m, v_ora, w_ora, rec["pi"].numpy())
+
+
 def _check(planner, reqs, done):
     for tag, (w, m) in enumerate(reqs):
         rec = done[tag]
@@ -75,7 +90,7 @@ def _check(planner, reqs, done):
         assert rec["v_start"] == float(v[p["start_j"] * p["nx"] + p["start_i"]]), tag
 
 
-def test_served_equals_plain(planner):
+def test_served_equals_plain(planner, ora):
     from paper_2109_00857_amd import mdp
 
     reqs = _requests()
@@ -85,6 +100,28 @@ def test_served_equals_plain(planner):
     info = srv.info()
     assert info["queued"] == 0 and info["in_flight"] == 0 and info["pool_used"] == 0, info
     _check(planner, reqs, done)
+    _check_oracle(ora, reqs, done)
+    srv.close()
+
+
+def test_served_both_lanes_chunked(planner, ora):
+    """Small thresholds send the larger requests to the large-build lane and split
+    every build batch into several persistent launches of a few tiles each, with
+    up to kServeAhead of them in flight per lane and both lanes building at once:
+    each result equals its plain solve bit for bit and the oracle's within
+    tolerance."""
+    from paper_2109_00857_amd import mdp
+
+    reqs = _requests()
+    envs = [planner.upload_env(w) for w, _ in reqs]
+    costs = sorted(w.n_rows * w.problem["n_real"] for w, _ in reqs)
+    large = float(costs[len(costs) // 2])  # about half the requests take the large lane
+    srv = mdp.Server(planner, pool_bytes=1 << 30, max_inflight=6, sweeps_per_step=2, chunk_cost=2e6,
+                     large_cost=large)
+    done = _run(srv, reqs, envs, per_step=4)
+    assert srv.info()["pool_used"] == 0
+    _check(planner, reqs, done)
+    _check_oracle(ora, reqs, done)
     srv.close()
 
 

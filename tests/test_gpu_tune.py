@@ -34,8 +34,10 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", [0, 1, 2])
-def test_every_launch_shape_gives_the_same_model(planner, case):
+def test_every_launch_shape_gives_the_same_model(planner, ora, case):
     from paper_2109_00857_amd import mdp
+
+    from gpu_helpers import assert_counts_equal, assert_rewards_close, model_to_host
 
     name, w = _cases()[case]
     p = w.problem
@@ -43,6 +45,12 @@ def test_every_launch_shape_gives_the_same_model(planner, case):
     mdp.mdp_ctx_set_plan(planner.ctx, p, 0, 0, 0)
     ref, ref_st = planner.build(p, env)
     assert ref_st["status"] == 0
+    # the default shape's model is the oracle's (every other shape is compared with it bit for bit)
+    om = ora.build_model(w)
+    assert ref_st["nnz"] == om["nnz"] and ref_st["n_near_edge"] in (-1, om["n_near_edge"])
+    g = model_to_host(ref, ref_st)
+    assert_counts_equal(g, om)
+    assert_rewards_close(g, om, w.missions())
     rep = mdp.mdp_autotune(planner.ctx, p, env)
     shapes = rep["shapes"]
     print(f"[tune] {name}: {len(shapes)} shapes, best {shapes[rep['best']]}", flush=True)
