@@ -7,7 +7,7 @@ import pytest
 
 from paper_2109_00857_amd import workloads as W
 
-from gpu_helpers import (assert_counts_equal, assert_policy_optimal, assert_rewards_close,
+from gpu_helpers import (REL_TOL, assert_counts_equal, assert_policy_optimal, assert_rewards_close,
                          assert_values_close, model_to_host)
 
 pytestmark = pytest.mark.gpu
@@ -311,7 +311,11 @@ def test_two_speed_corridor(planner, ora, case):
     v, _ = planner.value_iterate(p, model, c["mission"])
     pi = planner.policy(p, model, c["mission"], v).cpu().numpy()
     s0 = s["start"][1] * s["nx"] + s["start"][0]
-    assert abs(float(v[s0]) - c["v_start"]) < 1e-12 and pi[s0] == c["pi_start"]
+    # rewards are stored in fp32 (99.36 = r_term - 0.64 is not a float), so the
+    # start value holds within the value tolerance of the rewards' scale
+    _, _, w_ora = ora.backward(w, om, c["mission"])
+    assert abs(float(v[s0]) - c["v_start"]) <= REL_TOL * w_ora[s0], (float(v[s0]), c["v_start"], w_ora[s0])
+    assert pi[s0] == c["pi_start"]
 
 
 def test_swept_path_obstacles(planner, ora):

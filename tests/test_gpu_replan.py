@@ -96,7 +96,8 @@ def test_build_from_equals_full_rebuild(planner, ora, t0):
 def test_build_from_capacity_and_arguments(planner):
     from paper_2109_00857_amd import mdp
 
-    w = W.config1(nt=5, n_real=200, sub_h=3)
+    # a sub-grid wide enough for three times the spread (7 x 4 half widths needed)
+    w = W.config1(nt=5, n_real=200, sub_h=7)
     p = w.problem
     env = planner.upload_env(w)
     model, st0 = planner.build(p, env)
@@ -108,6 +109,7 @@ def test_build_from_capacity_and_arguments(planner):
     scratch = planner.scratch(p)
     st = mdp.stats_buffer(mdp.MdpBuildStats)
     small = {k: v for k, v in model.items()}
+    assert ref_st["status"] == 0 and ref_st["nnz"] > st0["nnz"], (ref_st, st0)
     if ref_st["nnz"] > st0["nnz"]:  # the current capacity (st0 nnz) is too small for the new model
         mdp.mdp_build_from(planner.ctx, p, env2, small, 2, scratch, st)
         assert mdp.mdp_build_sync(planner.ctx, st) == mdp.MDP_E_CAPACITY
