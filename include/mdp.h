@@ -215,6 +215,30 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
                              void *scratch, size_t scratch_bytes, mdp_vi_stats *stats,
                              void *stream);
 
+/* Bytes of the library's static device scratch used by
+ * mdp_value_iterate_noalloc (one copy per GPU, held until the process ends):
+ * the sweep state, device stats, the second fp64 value buffer [N_s] and the
+ * per-workgroup residuals, i.e. problems of up to about 9.4 million states. */
+#define MDP_NOALLOC_SCRATCH_BYTES ((size_t)72 << 20)
+
+/* mdp_value_iterate without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The call allocates nothing: its scratch
+ * is the library's static per-GPU array of MDP_NOALLOC_SCRATCH_BYTES, whose
+ * address the context looked up at mdp_ctx_create; it runs the same kernels
+ * as mdp_value_iterate and gives the same d_v and stats bit for bit. The
+ * caller still owns d_v (v0 in, result out, fp64 [N_s]) and the host stats.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call initialises what it reads before reading it):
+ * calls that overlap in time on one GPU (on different streams, or from
+ * several host threads or contexts) race and must be ordered on one stream.
+ * Sweeps are not recorded by mdp_ctx_profile. Errors: MDP_E_SCRATCH when the
+ * problem needs more than MDP_NOALLOC_SCRATCH_BYTES (the text gives the
+ * figure), MDP_E_INVALID as mdp_value_iterate, MDP_E_HIP if the context could
+ * not look up the array. */
+mdp_status mdp_value_iterate_noalloc(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
+                                     double tol, int32_t max_sweeps, double *d_v, mdp_vi_stats *stats, void *stream);
+
 /* Value iteration of the decision layers [t_first, nt) only (re-planning from
  * layer t_first on: every transition goes from layer t to t + 1 or to a sink,
  * so those layers depend on nothing earlier). The values of layers < t_first

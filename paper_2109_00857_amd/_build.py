@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["build.hip", "vi.hip", "rollout.hip", "api.hip"]
+SOURCES = ["build.hip", "vi.hip", "rollout.hip", "noalloc.hip", "api.hip"]
 LIB = os.path.join(PKG, "libmdp.so")
 
 HIPCC_FLAGS = [

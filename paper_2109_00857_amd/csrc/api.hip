@@ -40,6 +40,8 @@ struct TuneKey {
 struct mdp_ctx {
   int device;
   unsigned int *d_small;  // 256 bytes of device memory for synchronous helpers
+  void *d_noalloc = nullptr;  // this device's copy of the allocation-free VI scratch
+  char noalloc_err[128] = {};
   std::vector<std::pair<TuneKey, PlanChoice>> tuned;  // per shape class, from mdp_autotune / mdp_ctx_set_plan
   char err[512];
   // per-kernel timing (only while profiling is enabled)
@@ -429,6 +431,13 @@ mdp_status mdp_ctx_create(int32_t device, mdp_ctx **out)
   ctx->device = device;
   ctx->err[0] = 0;
   hipError_t e = hipMalloc((void **)&ctx->d_small, 256);
+  if (e == hipSuccess) {  // with `device` current: the device's copy of the static scratch
+    const hipError_t es = noalloc_scratch(device, &ctx->d_noalloc);
+    if (es != hipSuccess) {
+      ctx->d_noalloc = nullptr;
+      snprintf(ctx->noalloc_err, sizeof(ctx->noalloc_err), "%s", hipGetErrorString(es));
+    }
+  }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     delete ctx;
@@ -905,24 +914,17 @@ static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *
   return MDP_OK;
 }
 
-mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
-                             double tol, int32_t max_sweeps, double *d_v, void *scratch, size_t scratch_bytes,
-                             mdp_vi_stats *stats, void *stream)
+}  // extern "C"
+
+// Sweeps of one mission over layers [t_first, nt) from the values in d_v, on
+// the value-iteration scratch at sc (at least pl.vi_bytes: sweep state, device
+// stats, second value buffer, per-workgroup residuals), then the stats copy.
+// `timed`: record the sweeps in the context's profile.
+static mdp_status vi_run(mdp_ctx *ctx, const mdp_problem *p, VIParams &V, int t_first, double tol,
+                         int32_t max_sweeps, double *d_v, char *sc, mdp_vi_stats *stats, void *stream, bool timed)
 {
-  Plan pl;
-  VIParams V;
-  mdp_status rc = vi_setup(ctx, p, model, mission, pl, V);
-  if (rc != MDP_OK) return rc;
-  if (!is_device_ptr(d_v) || !stats || max_sweeps < 0) {
-    set_err(ctx, "d_v must be a device pointer, stats non-NULL, max_sweeps >= 0");
-    return MDP_E_INVALID;
-  }
-  if (!is_device_ptr(scratch) || scratch_bytes < pl.vi_bytes) {
-    set_err(ctx, "scratch needs %zu device bytes", pl.vi_bytes);
-    return MDP_E_SCRATCH;
-  }
-  char *sc = (char *)scratch;
   V.st = (VIState *)sc;
+  V.t_lo = t_first;
   mdp_vi_stats *dstats = (mdp_vi_stats *)(sc + align_up(sizeof(VIState)));
   double *v_alt = (double *)(sc + align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)));
   double *wg_res = (double *)((char *)v_alt + align_up((size_t)V.ns * 8));
@@ -931,13 +933,14 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   hipError_t e;
   if ((e = launch_vi_init(V.st, 1, s)) != hipSuccess) return hip_fail(ctx, e, "vi init");
   // The model is layered in time, so a positive tolerance is met after at most
-  // nt + 1 sweeps (the last one has residual exactly 0): no host polling.
+  // nt - t_first + 1 sweeps (the last one has residual exactly 0): no host
+  // polling.
   int n = max_sweeps;
-  if (tol > 0.0) n = std::min(n, p->nt + 1);
+  if (tol > 0.0) n = std::min(n, p->nt - t_first + 1);
   for (int k = 0; k < n; ++k) {
     const double *vin = (k & 1) ? v_alt : d_v;
     double *vout = (k & 1) ? d_v : v_alt;
-    Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
+    Timed tm(timed ? ctx : nullptr, MDP_KERNEL_VI_SWEEP, s);
     if ((e = launch_vi_sweep(V, vin, vout, vi_active_layers(p->nt, k), wg_res, s)) != hipSuccess)
       return hip_fail(ctx, e, "vi sweep");
   }
@@ -945,6 +948,16 @@ mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model
   if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_vi_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(ctx, e, "vi stats copy");
   return MDP_OK;
+}
+
+extern "C" {
+
+mdp_status mdp_value_iterate(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
+                             double tol, int32_t max_sweeps, double *d_v, void *scratch, size_t scratch_bytes,
+                             mdp_vi_stats *stats, void *stream)
+{
+  return mdp_value_iterate_layers(ctx, p, model, mission, 0, tol, max_sweeps, d_v, scratch, scratch_bytes, stats,
+                                  stream);
 }
 
 mdp_status mdp_value_iterate_layers(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
@@ -967,30 +980,30 @@ mdp_status mdp_value_iterate_layers(mdp_ctx *ctx, const mdp_problem *p, const md
     set_err(ctx, "scratch needs %zu device bytes", pl.vi_bytes);
     return MDP_E_SCRATCH;
   }
-  char *sc = (char *)scratch;
-  V.st = (VIState *)sc;
-  V.t_lo = t_first;
-  mdp_vi_stats *dstats = (mdp_vi_stats *)(sc + align_up(sizeof(VIState)));
-  double *v_alt = (double *)(sc + align_up(sizeof(VIState)) + align_up(sizeof(mdp_vi_stats)));
-  double *wg_res = (double *)((char *)v_alt + align_up((size_t)V.ns * 8));
-  V.tol = tol;
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e;
-  if ((e = launch_vi_init(V.st, 1, s)) != hipSuccess) return hip_fail(ctx, e, "vi init");
-  // Layers [t_first, nt) depend only on each other: nt - t_first + 1 sweeps at most.
-  int n = max_sweeps;
-  if (tol > 0.0) n = std::min(n, p->nt - t_first + 1);
-  for (int k = 0; k < n; ++k) {
-    const double *vin = (k & 1) ? v_alt : d_v;
-    double *vout = (k & 1) ? d_v : v_alt;
-    Timed tm(ctx, MDP_KERNEL_VI_SWEEP, s);
-    if ((e = launch_vi_sweep(V, vin, vout, vi_active_layers(p->nt, k), wg_res, s)) != hipSuccess)
-      return hip_fail(ctx, e, "vi sweep");
+  return vi_run(ctx, p, V, t_first, tol, max_sweeps, d_v, (char *)scratch, stats, stream, true);
+}
+
+mdp_status mdp_value_iterate_noalloc(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model, int32_t mission,
+                                     double tol, int32_t max_sweeps, double *d_v, mdp_vi_stats *stats, void *stream)
+{
+  Plan pl;
+  VIParams V;
+  mdp_status rc = vi_setup(ctx, p, model, mission, pl, V);
+  if (rc != MDP_OK) return rc;
+  if (pl.vi_bytes > MDP_NOALLOC_SCRATCH_BYTES) {
+    set_err(ctx, "value iteration of %lld states needs %zu scratch bytes, above the %zu of the allocation-free path",
+            (long long)V.ns, pl.vi_bytes, (size_t)MDP_NOALLOC_SCRATCH_BYTES);
+    return MDP_E_SCRATCH;
   }
-  if ((e = launch_vi_finish(V, d_v, v_alt, dstats, s)) != hipSuccess) return hip_fail(ctx, e, "vi finish");
-  if ((e = hipMemcpyAsync(stats, dstats, sizeof(mdp_vi_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
-    return hip_fail(ctx, e, "vi stats copy");
-  return MDP_OK;
+  if (!is_device_ptr(d_v) || !stats || max_sweeps < 0) {
+    set_err(ctx, "d_v must be a device pointer, stats non-NULL, max_sweeps >= 0");
+    return MDP_E_INVALID;
+  }
+  if (!ctx->d_noalloc) {
+    set_err(ctx, "the allocation-free scratch of device %d was not set up: %s", ctx->device, ctx->noalloc_err);
+    return MDP_E_HIP;
+  }
+  return vi_run(ctx, p, V, 0, tol, max_sweeps, d_v, (char *)ctx->d_noalloc, stats, stream, false);
 }
 
 mdp_status mdp_value_iterate_missions(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *model,

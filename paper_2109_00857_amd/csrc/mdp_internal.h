@@ -294,4 +294,9 @@ struct RollParams {
 
 hipError_t launch_rollout(const RollParams &P, mdp_rollout_stats *dev_stats, hipStream_t s);
 
+// The calling thread's current device, which must be `device`: the address of
+// that device's copy of the allocation-free value-iteration scratch
+// (noalloc.hip), looked up once per device.
+hipError_t noalloc_scratch(int device, void **out);
+
 }  // namespace mdpk

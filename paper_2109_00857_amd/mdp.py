@@ -142,6 +142,8 @@ def load():
                                           vp, C.c_size_t, vp, vp], C.c_int32),
             "mdp_value_iterate": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp,
                                    C.c_size_t, vp, vp], C.c_int32),
+            "mdp_value_iterate_noalloc": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.c_double, C.c_int32, vp, vp, vp],
+                                          C.c_int32),
             "mdp_value_iterate_missions": ([vp, P, C.POINTER(MdpModel), C.c_int32, C.POINTER(C.c_int32),
                                             C.c_double, C.c_int32, C.POINTER(vp), vp, C.c_size_t, vp, vp],
                                            C.c_int32),
@@ -180,7 +182,7 @@ def load():
 
 EXPORTED = ["mdp_ctx_create", "mdp_ctx_destroy", "mdp_status_str", "mdp_last_error", "mdp_build_query",
             "mdp_subgrid_auto", "mdp_build", "mdp_build_sync", "mdp_build_from", "mdp_value_iterate",
-            "mdp_value_iterate_layers", "mdp_value_iterate_missions",
+            "mdp_value_iterate_layers", "mdp_value_iterate_noalloc", "mdp_value_iterate_missions",
             "mdp_policy", "mdp_rollout_query", "mdp_rollout",
             "mdp_ctx_profile",
             "mdp_ctx_profile_read", "mdp_batch_query", "mdp_batch_create", "mdp_batch_build", "mdp_batch_solve",
@@ -298,6 +300,19 @@ def mdp_value_iterate(ctx, problem: dict, model: dict, mission: int, tol: float,
                                   _ptr(v), _ptr(scratch), scratch.numel(), stats.data_ptr(),
                                   _stream_handle(stream))
     _check(ctx, rc, "mdp_value_iterate")
+
+
+def mdp_value_iterate_noalloc(ctx, problem: dict, model: dict, mission: int, tol: float, max_sweeps: int,
+                              v: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
+    """mdp_value_iterate on the library's static per-GPU scratch (no allocation)."""
+    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
+                 int(model["col"].numel()))
+    rc = load().mdp_value_iterate_noalloc(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, tol,
+                                          max_sweeps, _ptr(v), stats.data_ptr(), _stream_handle(stream))
+    _check(ctx, rc, "mdp_value_iterate_noalloc")
+
+
+MDP_NOALLOC_SCRATCH_BYTES = 72 << 20
 
 
 def mdp_value_iterate_missions(ctx, problem: dict, model: dict, missions, tol: float, max_sweeps: int,
