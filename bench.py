@@ -208,7 +208,7 @@ def replan_leg(pl, w, p, env, vs, missions, reps: int = 3) -> dict:
 
 
 def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, near_edge: bool = False,
-             extras: bool = False) -> dict:
+             extras: bool = False, shape=None) -> dict:
     """Time `steps` planning steps of workload w (after `warmup` untimed ones):
     build + value iteration of every mission + policies. Returns the step time,
     the per-kernel rates and the rooflines of the build and the sweep; with
@@ -223,7 +223,11 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
         p["flags"] |= mdp.MDP_FLAG_NEAR_EDGE
     missions = w.missions()
     env = pl.upload_env(w)
-    tune = mdp.mdp_autotune(pl.ctx, p, env) if autotune else None  # untimed: the build launch shape
+    tune = None
+    if shape is not None:  # a given build launch shape (row lanes, realizations per chunk, 16-bit counters)
+        mdp.mdp_ctx_set_plan(pl.ctx, p, *shape)
+    elif autotune:
+        tune = mdp.mdp_autotune(pl.ctx, p, env)  # untimed: the build launch shape
     sizes = mdp.mdp_build_query(p)
     model, st0 = pl.build(p, env)  # sizes the model (untimed)
     assert st0["status"] == mdp.MDP_OK, st0
@@ -327,8 +331,9 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
         vi_launches_per_s=1e3 / (ms_v / n_v),  # fused sweeps (all missions)
         vi_sweeps_per_step=sweeps_per_step, vi_ms_per_step=ms_v / steps,
         policy_ms_per_step=kt[mdp.MDP_KERNEL_POLICY][1] / steps, copy_ms_per_step=kt[mdp.MDP_KERNEL_COPY][1] / steps,
-        build_shape=(None if tune is None else dict(tune["shapes"][tune["best"]], sample_layers=tune["sample_layers"],
-                                                     default_ms=tune["shapes"][tune["default"]]["ms"])),
+        build_shape=(dict(zip(("row_lanes", "rch", "pack16"), shape), given=True) if shape is not None else
+                     None if tune is None else dict(tune["shapes"][tune["best"]], sample_layers=tune["sample_layers"],
+                                                    default_ms=tune["shapes"][tune["default"]]["ms"])),
         rooflines={"build": roof_build, "vi_sweep": roof_vi},
         dominant="build" if ms_b >= ms_v else "vi_sweep",
     )
@@ -579,6 +584,9 @@ def main():
                     help="percent of the GPU's resident workgroups a served build batch may hold")
     ap.add_argument("--serve-sweeps", type=int, default=32, help="most sweeps per served scheduler step")
     ap.add_argument("--no-autotune", action="store_true", help="build with the default launch shape")
+    ap.add_argument("--shape", type=str, default=None,
+                    help="build launch shape ROW_LANES,RCH,PACK16 for the headline workload instead of the "
+                         "autotuner's pick (e.g. to profile the tuned kernel without the tuner's launches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -603,8 +611,9 @@ def main():
     w = workload(args.workload)
     print(f"[bench] headline workload {args.workload}: {w.n_rows} rows, {w.nominal_samples:.3e} samples",
           file=sys.stderr, flush=True)
+    shape = None if args.shape is None else tuple(int(x) for x in args.shape.split(","))
     main_leg = step_leg(pl, w, args.workload, args.steps, args.warmup, autotune=not args.no_autotune,
-                        near_edge=args.near_edge, extras=not args.no_second)
+                        near_edge=args.near_edge, extras=not args.no_second, shape=shape)
     rf = main_leg["rooflines"]
     descr = {"large": "large single instance: 200x200 cells, 200 layers, 16 modes, 10000 AR(1) realizations, "
                       "32 headings, 7x7 sub-grid, 4 moving discs, net-energy mission",
