@@ -38,7 +38,12 @@ HBM_BW = 8.0e12                        # bytes/s
 # source the figure is reported null. FETCH_SIZE / WRITE_SIZE are already
 # scaled to bytes by the plain-copy calibration (FETCH x2.000, WRITE x1.000);
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
-MEASURED = {}
+MEASURED = {
+    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
+                               read=232473807, write=474688784, valu_insts=14415080717),
+    ("k_vi_sweep_missions<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="3d7b9f769a1a050b",
+                                              read=5056668957, write=32613455, valu_insts=499054330),
+}
 
 
 def _src_sha(src: str) -> str:
@@ -468,11 +473,18 @@ def served_leg(pl, seconds: float, rate: float, pool_gib: float = 48.0, build_sh
     n = len(reqs)
     samples = sum(w.nominal_samples for w, _ in reqs)
 
+    large = np.array([w.name.startswith("c2") for w, _ in reqs])
+
     def stats(lat, wall):
         a = np.array([lat[j] for j in range(n)]) * 1e3
+        by_class = {}
+        for cls, sel in (("paper_shaped", large), ("batched_mix", ~large)):
+            if sel.any():
+                by_class[cls] = dict(n=int(sel.sum()), p50_ms=float(np.percentile(a[sel], 50)),
+                                     p99_ms=float(np.percentile(a[sel], 99)), mean_ms=float(a[sel].mean()))
         return dict(p50_ms=float(np.percentile(a, 50)), p99_ms=float(np.percentile(a, 99)),
                     mean_ms=float(a.mean()), max_ms=float(a.max()), wall_s=wall,
-                    requests_per_s=n / wall, samples_per_s=samples / wall)
+                    requests_per_s=n / wall, samples_per_s=samples / wall, by_class=by_class)
 
     s = torch.cuda.Stream()
     srv = mdp.Server(pl, pool_bytes=int(pool_gib * (1 << 30)), max_inflight=64, sweeps_per_step=sweeps_per_step,

@@ -1886,9 +1886,27 @@ struct BuildLane {
   int64_t pool_cap = 0;
   int n_items = 0;
   mdp_build_stats *bstats = nullptr;
+  // Large lane only: once its build batch is done, the batch's whole solve
+  // runs on the lane's stream (cold start, every sweep a few launches at a
+  // time as for the build, finish, policy, results into pinned memory), so a
+  // large request neither waits for the caller's steps nor makes the small
+  // requests' steps carry its sweeps.
+  std::vector<ServeReq *> solving;  // the batch being solved
+  Block sblk;                       // its block-start tables, inside the pool
+  int64_t *d_stabs = nullptr;       // [solve_k][n + 1] per sweep, then [n + 1] for the policy
+  int solve_k = 0, solve_next = 0;  // sweeps to enqueue, enqueued
+  bool solve_tail = false;          // finish, policy, copies and solve_ev enqueued
+  size_t solve_win = 0;
+  hipEvent_t solve_ev = nullptr;
+  BatchVIDesc *d_svdesc = nullptr;  // [max_inflight]
+  double *d_swg = nullptr;          // [kBatchViGrid][max_inflight]
+  mdp_vi_stats *d_sstat = nullptr;  // [max_inflight]
+  Pinned h_svdesc, h_stabs, h_sfstat, h_svstart;
 };
 
 constexpr int kServeLanes = 2;  // 0: small builds, 1: large builds
+constexpr int kServeSolveLane = 1;  // the lane whose batches are solved on their own stream
+constexpr int kServeSolveGroup = 8;  // sweeps per pumped launch group of a lane solve
 
 struct mdp_server {
   mdp_ctx *ctx = nullptr;
@@ -1919,6 +1937,12 @@ struct mdp_server {
     for (const BuildLane &L : lane) k += L.building.size();
     return k;
   }
+  size_t n_solving() const
+  {
+    size_t k = 0;
+    for (const BuildLane &L : lane) k += L.solving.size();
+    return k;
+  }
 };
 
 namespace {
@@ -1926,14 +1950,16 @@ namespace {
 void serve_free_all(mdp_server *S)
 {
   for (BuildLane &L : S->lane) {
-    if (L.stream && !L.building.empty()) (void)hipStreamSynchronize(L.stream);
+    if (L.stream && (!L.building.empty() || !L.solving.empty())) (void)hipStreamSynchronize(L.stream);
     for (ServeReq *r : L.building) delete r;
+    for (ServeReq *r : L.solving) delete r;
     for (hipEvent_t ev : L.ahead)
       if (ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {L.d_bdesc, L.d_tabs};
+    void *bufs[] = {L.d_bdesc, L.d_tabs, L.d_svdesc, L.d_swg, L.d_sstat};
     for (void *p : bufs)
       if (p) (void)hipFree(p);
     if (L.event) (void)hipEventDestroy(L.event);
+    if (L.solve_ev) (void)hipEventDestroy(L.solve_ev);
     if (L.stream) (void)hipStreamDestroy(L.stream);
   }
   if (S->sync_ev) (void)hipEventDestroy(S->sync_ev);
@@ -2069,6 +2095,8 @@ mdp_status serve_pump(mdp_server *S, BuildLane &L)
   return MDP_OK;
 }
 
+mdp_status serve_pump_solve(mdp_server *S, BuildLane &L);
+
 // Wait for the work enqueued so far on stream s, keeping the build lanes fed
 // meanwhile.
 hipError_t serve_wait(mdp_server *S, hipStream_t s)
@@ -2078,8 +2106,10 @@ hipError_t serve_wait(mdp_server *S, hipStream_t s)
   for (;;) {
     e = hipEventQuery(S->sync_ev);
     if (e != hipErrorNotReady) return e;
-    for (BuildLane &L : S->lane)
+    for (BuildLane &L : S->lane) {
       if (!L.building.empty() && serve_pump(S, L) != MDP_OK) return hipErrorUnknown;
+      if (!L.solving.empty() && serve_pump_solve(S, L) != MDP_OK) return hipErrorUnknown;
+    }
     std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
 }
@@ -2217,7 +2247,7 @@ mdp_status serve_admit(mdp_server *S, int li)
   std::vector<ServeReq *> &fresh = L.building;
   Block &bblk = L.blk;
   for (auto it = S->queue.begin(); it != S->queue.end();) {
-    if ((int)(S->running.size() + S->n_building()) >= S->cfg.max_inflight) break;
+    if ((int)(S->running.size() + S->n_building() + S->n_solving()) >= S->cfg.max_inflight) break;
     ServeReq *r = *it;
     if (lane_of(S, r) != li) {
       ++it;
@@ -2260,6 +2290,127 @@ size_t vi_descs(const std::vector<ServeReq *> &reqs, BatchVIDesc *vd)
     batch_vi_desc(&r->p, req_model(r), r->pl, r->mission, r->v, r->v_alt, r->pi, r->st, vd[i]);
   }
   return batch_win_bytes(vd, (int)reqs.size());
+}
+
+// Enqueue the lane solve's sweeps, kServeSolveGroup at a time with at most
+// kServeAhead groups in flight, then its tail: finish (values back into v,
+// stats), policy, and each request's start value, policy and values into
+// pinned host memory, then solve_ev.
+mdp_status serve_pump_solve(mdp_server *S, BuildLane &L)
+{
+  hipStream_t s = L.stream;
+  hipError_t e;
+  const int n = (int)L.solving.size();
+  while (L.solve_next < L.solve_k) {
+    if (L.ahead_n == kServeAhead) {
+      const hipError_t q = hipEventQuery(L.ahead[L.ahead_head]);
+      if (q == hipErrorNotReady) return MDP_OK;
+      if (q != hipSuccess) return hip_fail(S->ctx, q, "serve solve");
+      L.ahead_head = (L.ahead_head + 1) % kServeAhead;
+      --L.ahead_n;
+    }
+    const int g = std::min(kServeSolveGroup, L.solve_k - L.solve_next);
+    for (int j = L.solve_next; j < L.solve_next + g; ++j) {
+      Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
+      if ((e = launch_vi_sweep_batched(L.d_svdesc, n, L.d_stabs + (size_t)j * (n + 1), L.d_swg, kBatchViGrid,
+                                       L.solve_win, s)) != hipSuccess ||
+          (e = launch_vi_close_batched(L.d_svdesc, n, kBatchViGrid, L.d_swg, S->cfg.tol, s)) != hipSuccess)
+        return hip_fail(S->ctx, e, "serve solve sweep");
+    }
+    if ((e = hipEventRecord(L.ahead[(L.ahead_head + L.ahead_n) % kServeAhead], s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve solve");
+    ++L.ahead_n;
+    L.solve_next += g;
+  }
+  if (L.solve_tail) return MDP_OK;
+  if ((e = launch_vi_finish_batched(L.d_svdesc, n, L.d_sstat, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve finish");
+  {
+    Timed tm(S->ctx, MDP_KERNEL_POLICY, s);
+    if ((e = launch_policy_batched(L.d_svdesc, n, L.d_stabs + (size_t)L.solve_k * (n + 1), kBatchViGrid,
+                                   L.solve_win, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve solve policy");
+  }
+  double *vstart = L.h_svstart.as<double>();
+  for (int i = 0; i < n; ++i) {
+    ServeReq *r = L.solving[i];
+    const size_t ns = (size_t)r->z.ns;
+    const int64_t s0 = (int64_t)r->p.start_j * r->p.nx + r->p.start_i;
+    if ((e = hipMemcpyAsync(&vstart[i], r->v + s0, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (r->h_pi && (e = hipMemcpyAsync(r->h_pi, r->pi, 4 * ns, hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+        (r->h_v && (e = hipMemcpyAsync(r->h_v, r->v, 8 * ns, hipMemcpyDeviceToHost, s)) != hipSuccess))
+      return hip_fail(S->ctx, e, "serve solve results");
+  }
+  if ((e = hipMemcpyAsync(L.h_sfstat.p, L.d_sstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipEventRecord(L.solve_ev, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve end");
+  L.solve_tail = true;
+  return MDP_OK;
+}
+
+// The lane's build batch has ended: record its build results and start its
+// solve on the lane's stream. Without pool room for the solve's block-start
+// tables the batch joins the caller's sweeps instead (serve_join).
+mdp_status serve_solve_start(mdp_server *S, BuildLane &L)
+{
+  const int n = (int)L.building.size();
+  int k = 1;
+  for (const ServeReq *r : L.building) k = std::max(k, r->limit);
+  const size_t tab_bytes = sizeof(int64_t) * (size_t)(n + 1) * (size_t)(k + 1);
+  serve_join(S, L);  // build stats, build block and unused model tails back to the pool; batch now in S->running
+  if (!take(S->alloc, L.sblk, tab_bytes)) return MDP_OK;
+  L.solving.assign(S->running.end() - n, S->running.end());
+  S->running.resize(S->running.size() - n);
+  hipStream_t s = L.stream;
+  hipError_t e;
+  if ((e = L.h_svdesc.ensure(sizeof(BatchVIDesc) * n)) != hipSuccess ||
+      (e = L.h_stabs.ensure(tab_bytes)) != hipSuccess ||
+      (e = L.h_sfstat.ensure(sizeof(mdp_vi_stats) * n)) != hipSuccess ||
+      (e = L.h_svstart.ensure(sizeof(double) * n)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve staging");
+  BatchVIDesc *vd = L.h_svdesc.as<BatchVIDesc>();
+  L.solve_win = vi_descs(L.solving, vd);
+  std::vector<int> behind(n, 0);
+  std::vector<int64_t> tabs;
+  active_block_tables(vd, behind.data(), n, k, tabs);  // cold start: sweep j recomputes layers < nt - j + 1
+  tabs.resize((size_t)(n + 1) * (k + 1));
+  int64_t *full = &tabs[(size_t)k * (n + 1)];  // every block, for the policy
+  full[0] = 0;
+  for (int i = 0; i < n; ++i) full[i + 1] = full[i] + vd[i].P.n_blocks;
+  memcpy(L.h_stabs.p, tabs.data(), tab_bytes);
+  L.d_stabs = (int64_t *)(S->pool + L.sblk.off);
+  if ((e = hipMemcpyAsync(L.d_svdesc, vd, sizeof(BatchVIDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(L.d_stabs, L.h_stabs.p, tab_bytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = launch_vi_reset_batched(L.d_svdesc, n, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve start");
+  for (ServeReq *r : L.solving) r->cold = false;
+  L.solve_k = k;
+  L.solve_next = 0;
+  L.solve_tail = false;
+  L.ahead_head = L.ahead_n = 0;  // every build launch's event has completed with the build's tail
+  return serve_pump_solve(S, L);
+}
+
+// The lane's solve has ended: completion records, model memory back to the pool.
+void serve_solve_retire(mdp_server *S, BuildLane &L)
+{
+  const mdp_vi_stats *hf = L.h_sfstat.as<mdp_vi_stats>();
+  const double *vstart = L.h_svstart.as<double>();
+  for (size_t i = 0; i < L.solving.size(); ++i) {
+    ServeReq *r = L.solving[i];
+    r->res.sweeps = hf[i].sweeps;
+    r->res.residual = hf[i].residual;
+    r->res.v_start = vstart[i];
+    r->res.status = r->res.build_status != MDP_OK ? r->res.build_status : hf[i].status;
+    r->res.done_step = S->step_no;
+    S->done.push_back(r->res);
+    unreserve(S, r);
+    delete r;
+  }
+  L.solving.clear();
+  give(S->alloc, L.sblk);
+  L.d_stabs = nullptr;
 }
 
 }  // namespace
@@ -2317,6 +2468,16 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
       serve_free_all(S);
       return hip_fail(ctx, e, "server build lanes");
     }
+  {
+    BuildLane &L = S->lane[kServeSolveLane];
+    if ((e = hipEventCreateWithFlags(&L.solve_ev, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipMalloc((void **)&L.d_svdesc, sizeof(BatchVIDesc) * n)) != hipSuccess ||
+        (e = hipMalloc((void **)&L.d_swg, sizeof(double) * kBatchViGrid * n)) != hipSuccess ||
+        (e = hipMalloc((void **)&L.d_sstat, sizeof(mdp_vi_stats) * n)) != hipSuccess) {
+      serve_free_all(S);
+      return hip_fail(ctx, e, "server solve lane");
+    }
+  }
   if ((e = hipEventCreateWithFlags(&S->sync_ev, hipEventDisableTiming)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vret, sizeof(BatchVIDesc) * n)) != hipSuccess ||
@@ -2399,7 +2560,21 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
     const auto t_end = std::chrono::steady_clock::now() + std::chrono::microseconds(kServeWaitUs);
     for (;;) {
       bool joined = false, busy = false;
-      for (BuildLane &L : S->lane) {
+      for (int li = 0; li < kServeLanes; ++li) {
+        BuildLane &L = S->lane[li];
+        if (!L.solving.empty()) {  // the large lane's solve: keep it fed, retire it when it ends
+          if (mdp_status pr = serve_pump_solve(S, L); pr != MDP_OK) return pr;
+          const hipError_t q = L.solve_tail ? hipEventQuery(L.solve_ev) : hipErrorNotReady;
+          if (q == hipSuccess) {
+            serve_solve_retire(S, L);
+            joined = true;
+          } else if (q == hipErrorNotReady) {
+            busy = true;
+          } else {
+            return hip_fail(S->ctx, q, "serve solve");
+          }
+          continue;
+        }
         if (L.building.empty()) continue;
         if (mdp_status pr = serve_pump(S, L); pr != MDP_OK) return pr;
         if (!L.tail) {
@@ -2408,7 +2583,11 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
         }
         hipError_t q = hipEventQuery(L.event);
         if (q == hipSuccess) {
-          serve_join(S, L);
+          if (li == kServeSolveLane) {
+            if (mdp_status pr = serve_solve_start(S, L); pr != MDP_OK) return pr;
+          } else {
+            serve_join(S, L);
+          }
           joined = true;
         } else if (q == hipErrorNotReady) {
           busy = true;
@@ -2422,18 +2601,18 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   };
   auto admit_idle = [&]() -> mdp_status {
     for (int li = 0; li < kServeLanes; ++li)
-      if (S->lane[li].building.empty() && !S->queue.empty()) {
+      if (S->lane[li].building.empty() && S->lane[li].solving.empty() && !S->queue.empty()) {
         mdp_status r2 = serve_admit(S, li);
         if (r2 != MDP_OK) return r2;
       }
     return MDP_OK;
   };
   if ((rc = poll_lanes(false)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
-  if (S->running.empty() && S->n_building() > 0) {  // nothing to sweep until a build ends
+  if (S->running.empty() && S->n_building() + S->n_solving() > 0) {  // nothing to sweep until a lane ends
     if ((rc = poll_lanes(true)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
   }
   if (S->running.empty()) {
-    if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building());
+    if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building() + S->n_solving());
     return MDP_OK;
   }
   // ---- sweeps, shortest remaining work first, without starving the oldest:
@@ -2555,7 +2734,7 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
   keep.insert(keep.end(), paused.begin(), paused.end());
   keep_paused.armed = false;
   S->running.swap(keep);
-  if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building() + S->running.size());
+  if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building() + S->n_solving() + S->running.size());
   return MDP_OK;
 }
 
@@ -2573,7 +2752,7 @@ mdp_status mdp_server_info(mdp_server *S, mdp_server_state *out)
 {
   if (!S || !out) return MDP_E_INVALID;
   out->queued = (int32_t)S->queue.size();
-  out->in_flight = (int32_t)(S->n_building() + S->running.size());
+  out->in_flight = (int32_t)(S->n_building() + S->n_solving() + S->running.size());
   out->completed = (int32_t)S->done.size();
   out->pad = 0;
   out->pool_used = (int64_t)S->alloc.used();
