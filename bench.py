@@ -43,6 +43,11 @@ MEASURED = {
                                read=232473807, write=474688784, valu_insts=14415080717),
     ("k_vi_sweep_missions<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="3d7b9f769a1a050b",
                                               read=5056668957, write=32613455, valu_insts=499054330),
+    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
+                                      read=444055040, write=882345296, valu_insts=13582614500),
+    ("k_vi_sweep_missions<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
+                                                     sha256="3d7b9f769a1a050b", read=416390465, write=14990360,
+                                                     valu_insts=69516916),
 }
 
 
@@ -592,6 +597,9 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-trace leg")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the served trace")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrival rate (per second)")
+    ap.add_argument("--serve-rate-high", type=float, default=60.0,
+                    help="arrival rate of a second, shorter served trace at a higher load (0: skip)")
+    ap.add_argument("--serve-seconds-high", type=float, default=20.0, help="length of the higher-load trace")
     ap.add_argument("--build-share", type=int, default=100,
                     help="percent of the GPU's resident workgroups a served build batch may hold")
     ap.add_argument("--serve-sweeps", type=int, default=32, help="most sweeps per served scheduler step")
@@ -685,6 +693,12 @@ def main():
             out["p99_ms_served"] = out["served"]["served"]["p99_ms"]
         except Exception as e:
             out["served"] = {"error": repr(e)}
+        if args.serve_rate_high > 0:
+            try:
+                out["served_high_load"] = served_leg(pl, args.serve_seconds_high, args.serve_rate_high,
+                                                     build_share=args.build_share, sweeps_per_step=args.serve_sweeps)
+            except Exception as e:
+                out["served_high_load"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w)
         out["cpu_baseline"] = cb

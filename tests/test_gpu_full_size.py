@@ -66,8 +66,10 @@ def test_full_size_sampled(planner, ora, which):
     missions = w.missions()
     rng = np.random.default_rng(2024)
 
-    # ---- sampled rows
-    rows = np.sort(rng.choice(w.n_rows, N_ROWS, replace=False))
+    # ---- sampled rows, plus the rows on each side of the build passes' layer
+    # boundaries (the large instance is built 8 layers per pass)
+    edges = [b * nc * na + d for b in range(8, nt, 8) for d in (-1, 0)]
+    rows = np.unique(np.concatenate([rng.choice(w.n_rows, N_ROWS, replace=False), edges]))
     got = _rows_of(model, rows)
     import torch
 
@@ -88,8 +90,9 @@ def test_full_size_sampled(planner, ora, which):
     for s in states:
         t, c = divmod(int(s), nc)
         oracle_rows[int(s)] = [ora.row(w, t, c, a) for a in range(na)]
-    for m in missions:
-        v, vst = planner.value_iterate(p, model, m)
+    # the missions solved together, as the benchmark step does
+    vs, vsts = planner.value_iterate_missions(p, model, missions)
+    for m, v, vst in zip(missions, vs, vsts):
         assert vst["status"] == 0 and vst["sweeps"] <= nt + 1, vst
         pi = planner.policy(p, model, m, v).cpu().numpy()
         v = v.cpu().numpy()

@@ -288,6 +288,20 @@ def test_vi_missions_rejects_bad_arguments(planner):
     assert all(s["status"] == 0 for s in sts)
 
 
+def test_wide_grid_without_window(planner, ora):
+    """A grid too wide for the staged window of v(t + 1) (six grid rows of 520
+    cells exceed its 16 KB): the sweeps and the policy gather every successor's
+    value from memory; full parity, and the fused solve equals the single one."""
+    import torch
+
+    w = W.config2(nx=520, ny=7, nt=4, n_real=300, K=4, n_head=8)
+    p, env, model, stats, om = _full_parity(planner, ora, w, "wide grid, no window")
+    vs, _ = planner.value_iterate_missions(p, model, w.missions())
+    for m, v in zip(w.missions(), vs):
+        v1, _ = planner.value_iterate(p, model, m)
+        assert torch.equal(v, v1), m
+
+
 def test_paper_action_set_two_speeds(planner, ora):
     """The paper's application action set, 16 headings x 2 speeds, on config-2
     shapes with all three missions (ragged grid): full parity."""
