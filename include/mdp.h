@@ -416,11 +416,15 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
 /* Queue a request (no device work). MDP_E_CAPACITY if it can never fit the pool. */
 mdp_status mdp_server_submit(mdp_server *srv, const mdp_problem *p, const mdp_env *env, int32_t mission,
                              int32_t *h_pi, double *h_v, int64_t tag);
-/* One scheduler iteration on `stream`; n_active = queued + admitted afterwards.
- * Sweeps the built requests chosen this step (shortest remaining work first,
- * the earliest-submitted one always) and waits for them; with nothing built
- * to sweep it waits at most about 0.5 ms for a build, so callers loop on it
- * while n_active > 0 and submit new arrivals between calls. */
+/* One scheduler iteration on `stream` (the same stream on every call);
+ * n_active = queued + admitted afterwards. It admits queued requests into idle
+ * build lanes, retires the requests the last completed step found converged
+ * (finish, policy, copies into their pinned buffers) and enqueues the sweeps
+ * of the built requests chosen this step (shortest remaining work first, the
+ * earliest-submitted one always), then returns without waiting for them; a
+ * later call reads their status. While the previous step's sweeps run, or
+ * with nothing built to sweep, a call waits at most about 0.5 ms, so callers
+ * loop on it while n_active > 0 and submit new arrivals between calls. */
 mdp_status mdp_server_step(mdp_server *srv, void *stream, int32_t *n_active);
 /* Move up to max_out completion records (oldest first) into out. */
 mdp_status mdp_server_poll(mdp_server *srv, mdp_served *out, int32_t max_out, int32_t *n_out);

@@ -1918,11 +1918,19 @@ struct mdp_server {
   BuildLane lane[kServeLanes];
   std::vector<ServeReq *> running;  // built; swept on the caller's stream
   std::vector<mdp_served> done;     // completion records not yet polled
+  // A step enqueues its sweeps and returns; a later step reads their status
+  // once step_ev has completed. Converged requests wait in to_retire until
+  // their retirement (finish, policy, copies) is enqueued, then in retiring
+  // until ret_ev has completed.
+  bool step_inflight = false;
+  hipEvent_t step_ev = nullptr;
+  std::vector<ServeReq *> step_run;  // the requests the step in flight sweeps
+  std::vector<ServeReq *> to_retire, retiring;
+  hipEvent_t ret_ev = nullptr;
   int64_t step_no = 0;
   int64_t n_submitted = 0;
   double chunk_cost = 0.0;  // work of one build launch (cfg.chunk_cost or the default)
   double large_cost = 0.0;  // build cost above which a request takes the large lane
-  hipEvent_t sync_ev = nullptr;  // end of a step's work on the caller's stream
   // device tables, sized for cfg.max_inflight problems
   BatchVIDesc *d_vrun = nullptr, *d_vret = nullptr;
   int64_t *d_bs_ret = nullptr;
@@ -1962,9 +1970,18 @@ void serve_free_all(mdp_server *S)
     if (L.solve_ev) (void)hipEventDestroy(L.solve_ev);
     if (L.stream) (void)hipStreamDestroy(L.stream);
   }
-  if (S->sync_ev) (void)hipEventDestroy(S->sync_ev);
+  if (S->step_ev) {
+    if (S->step_inflight) (void)hipEventSynchronize(S->step_ev);
+    (void)hipEventDestroy(S->step_ev);
+  }
+  if (S->ret_ev) {
+    if (!S->retiring.empty()) (void)hipEventSynchronize(S->ret_ev);
+    (void)hipEventDestroy(S->ret_ev);
+  }
   for (ServeReq *r : S->queue) delete r;
   for (ServeReq *r : S->running) delete r;
+  for (ServeReq *r : S->to_retire) delete r;
+  for (ServeReq *r : S->retiring) delete r;
   void *bufs[] = {S->d_vrun, S->d_vret, S->d_bs_ret, S->d_bs_sweeps, S->d_wg_res, S->d_vstat};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
@@ -2095,24 +2112,6 @@ mdp_status serve_pump(mdp_server *S, BuildLane &L)
   return MDP_OK;
 }
 
-mdp_status serve_pump_solve(mdp_server *S, BuildLane &L);
-
-// Wait for the work enqueued so far on stream s, keeping the build lanes fed
-// meanwhile.
-hipError_t serve_wait(mdp_server *S, hipStream_t s)
-{
-  hipError_t e = hipEventRecord(S->sync_ev, s);
-  if (e != hipSuccess) return e;
-  for (;;) {
-    e = hipEventQuery(S->sync_ev);
-    if (e != hipErrorNotReady) return e;
-    for (BuildLane &L : S->lane) {
-      if (!L.building.empty() && serve_pump(S, L) != MDP_OK) return hipErrorUnknown;
-      if (!L.solving.empty() && serve_pump_solve(S, L) != MDP_OK) return hipErrorUnknown;
-    }
-    std::this_thread::sleep_for(std::chrono::microseconds(20));
-  }
-}
 
 // Start the batched build of the requests in L.building on the lane's stream:
 // descriptors through pinned staging, the work counters, then the persistent
@@ -2247,7 +2246,9 @@ mdp_status serve_admit(mdp_server *S, int li)
   std::vector<ServeReq *> &fresh = L.building;
   Block &bblk = L.blk;
   for (auto it = S->queue.begin(); it != S->queue.end();) {
-    if ((int)(S->running.size() + S->n_building() + S->n_solving()) >= S->cfg.max_inflight) break;
+    if ((int)(S->running.size() + S->to_retire.size() + S->retiring.size() + S->n_building() + S->n_solving()) >=
+        S->cfg.max_inflight)
+      break;
     ServeReq *r = *it;
     if (lane_of(S, r) != li) {
       ++it;
@@ -2478,7 +2479,8 @@ mdp_status mdp_server_create(mdp_ctx *ctx, const mdp_server_config *cfg, void *p
       return hip_fail(ctx, e, "server solve lane");
     }
   }
-  if ((e = hipEventCreateWithFlags(&S->sync_ev, hipEventDisableTiming)) != hipSuccess ||
+  if ((e = hipEventCreateWithFlags(&S->step_ev, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&S->ret_ev, hipEventDisableTiming)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vrun, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_vret, sizeof(BatchVIDesc) * n)) != hipSuccess ||
       (e = hipMalloc((void **)&S->d_bs_ret, sizeof(int64_t) * (n + 1))) != hipSuccess ||
@@ -2607,89 +2609,80 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
       }
     return MDP_OK;
   };
-  if ((rc = poll_lanes(false)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
-  if (S->running.empty() && S->n_building() + S->n_solving() > 0) {  // nothing to sweep until a lane ends
-    if ((rc = poll_lanes(true)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
-  }
-  if (S->running.empty()) {
-    if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building() + S->n_solving());
-    return MDP_OK;
-  }
-  // ---- sweeps, shortest remaining work first, without starving the oldest:
-  // this step sweeps the built requests whose remaining work (rows times
-  // sweeps still to run) is within kServeWorkRatio of the smallest, and the
-  // earliest-submitted built request in any case; the others wait (their
-  // state is untouched)
-  std::vector<ServeReq *> sweep, paused;
-  {
-    double wmin = 0.0;
-    const ServeReq *oldest = nullptr;
-    for (ServeReq *r : S->running) {
-      const double w = (double)r->z.rows * (r->limit - r->sweeps);
-      if (!oldest || w < wmin) wmin = w;
-      if (!oldest || r->seq < oldest->seq) oldest = r;
+  auto n_act = [&]() {
+    return (int32_t)(S->queue.size() + S->n_building() + S->n_solving() + S->running.size() + S->to_retire.size() +
+                     S->retiring.size());
+  };
+  // ---- completed retirements: records, memory back to the pool
+  auto finish_retire = [&]() {
+    const mdp_vi_stats *hf = S->h_fstat.as<mdp_vi_stats>();
+    const double *vstart = S->h_vstart.as<double>();
+    for (size_t i = 0; i < S->retiring.size(); ++i) {
+      ServeReq *r = S->retiring[i];
+      r->res.sweeps = hf[i].sweeps;
+      r->res.residual = hf[i].residual;
+      r->res.v_start = vstart[i];
+      r->res.status = r->res.build_status != MDP_OK ? r->res.build_status : hf[i].status;
+      r->res.done_step = S->step_no;
+      S->done.push_back(r->res);
+      unreserve(S, r);
+      delete r;
+    }
+    S->retiring.clear();
+  };
+  // ---- the step in flight has ended: its requests' status, converged ones to retire
+  auto finish_step = [&]() {
+    const mdp_vi_stats *hv = S->h_vstat.as<mdp_vi_stats>();
+    std::vector<ServeReq *> keep;
+    for (size_t i = 0; i < S->step_run.size(); ++i) {
+      ServeReq *r = S->step_run[i];
+      r->res.sweeps = hv[i].sweeps;
+      r->res.residual = hv[i].residual;
+      if (r->res.build_status != MDP_OK || hv[i].status == MDP_OK || r->sweeps >= r->limit) S->to_retire.push_back(r);
     }
     for (ServeReq *r : S->running)
-      (r == oldest || (double)r->z.rows * (r->limit - r->sweeps) <= kServeWorkRatio * wmin ? sweep : paused)
-          .push_back(r);
+      if (std::find(S->to_retire.begin(), S->to_retire.end(), r) == S->to_retire.end()) keep.push_back(r);
+    S->running.swap(keep);
+    S->step_run.clear();
+    S->step_inflight = false;
+  };
+  auto query = [&](hipEvent_t ev, bool &ended) -> mdp_status {
+    const hipError_t q = hipEventQuery(ev);
+    ended = q == hipSuccess;
+    if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(S->ctx, q, "serve step");
+    return MDP_OK;
+  };
+  bool ended = false;
+  if ((rc = poll_lanes(false)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
+  if (!S->retiring.empty()) {
+    if ((rc = query(S->ret_ev, ended)) != MDP_OK) return rc;
+    if (ended) finish_retire();
   }
-  S->running = sweep;
-  struct KeepPaused {  // paused requests return to the running set on every exit
-    std::vector<ServeReq *> &run, &paused;
-    bool armed = true;
-    ~KeepPaused()
-    {
-      if (armed) run.insert(run.end(), paused.begin(), paused.end());
+  if (S->step_inflight) {
+    if ((rc = query(S->step_ev, ended)) != MDP_OK) return rc;
+    if (ended) finish_step();
+  }
+  if (S->step_inflight) {  // the device is still on the last step's sweeps: wait for it a little
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::microseconds(kServeWaitUs);
+    for (;;) {
+      if ((rc = query(S->step_ev, ended)) != MDP_OK) return rc;
+      if (ended) {
+        finish_step();
+        break;
+      }
+      if ((rc = poll_lanes(false)) != MDP_OK) return rc;
+      if (std::chrono::steady_clock::now() >= t_end) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-  } keep_paused{S->running, paused};
-  const int n_run = (int)S->running.size();
-  BatchVIDesc *vd = S->h_vrun.as<BatchVIDesc>();
-  const size_t win = vi_descs(S->running, vd);
-  if ((e = hipMemcpyAsync(S->d_vrun, vd, sizeof(BatchVIDesc) * n_run, hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve solve descriptors");
-  for (int i = 0; i < n_run; ++i) {
-    ServeReq *r = S->running[i];
-    if (!r->cold) continue;
-    if ((e = launch_vi_reset_batched(S->d_vrun + i, 1, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve reset");
-    r->cold = false;
+    if (S->step_inflight) {
+      if (n_active) *n_active = n_act();
+      return MDP_OK;
+    }
   }
-  int k = S->cfg.sweeps_per_step;
-  for (ServeReq *r : S->running) k = std::min(k, r->limit - r->sweeps);
-  k = std::max(k, 1);
-  std::vector<int> behind(n_run);
-  for (int i = 0; i < n_run; ++i) behind[i] = S->running[i]->sweeps;
-  std::vector<int64_t> tabs;
-  active_block_tables(vd, behind.data(), n_run, k, tabs);
-  memcpy(S->h_tables.p, tabs.data(), sizeof(int64_t) * tabs.size());
-  if ((e = hipMemcpyAsync(S->d_bs_sweeps, S->h_tables.p, sizeof(int64_t) * tabs.size(), hipMemcpyHostToDevice, s)) !=
-      hipSuccess)
-    return hip_fail(S->ctx, e, "serve sweep tables");
-  for (int j = 0; j < k; ++j) {
-    Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
-    if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_sweeps + (size_t)j * (n_run + 1), S->d_wg_res,
-                                     kBatchViGrid, win, s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve sweep");
-    if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
-      return hip_fail(S->ctx, e, "serve close");
-  }
-  for (ServeReq *r : S->running) r->sweeps += k;
-  mdp_vi_stats *hv = S->h_vstat.as<mdp_vi_stats>();
-  if ((e = launch_vi_status_batched(S->d_vrun, n_run, S->d_vstat, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(hv, S->d_vstat, sizeof(mdp_vi_stats) * n_run, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = serve_wait(S, s)) != hipSuccess)
-    return hip_fail(S->ctx, e, "serve vi stats");
-  // ---- retire converged requests (and failed builds)
-  std::vector<ServeReq *> ret, keep;
-  for (int i = 0; i < n_run; ++i) {
-    ServeReq *r = S->running[i];
-    r->res.sweeps = hv[i].sweeps;
-    r->res.residual = hv[i].residual;
-    if (r->res.build_status != MDP_OK || hv[i].status == MDP_OK || r->sweeps >= r->limit)
-      ret.push_back(r);
-    else
-      keep.push_back(r);
-  }
-  if (!ret.empty()) {
+  // ---- retire converged requests (and failed builds): finish, policy, the
+  // results into the caller's pinned buffers, then ret_ev
+  if (!S->to_retire.empty() && S->retiring.empty()) {
+    std::vector<ServeReq *> &ret = S->to_retire;
     const int n = (int)ret.size();
     BatchVIDesc *rd = S->h_vret.as<BatchVIDesc>();
     const size_t rwin = vi_descs(ret, rd);
@@ -2706,7 +2699,6 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
         return hip_fail(S->ctx, e, "serve policy");
     }
     double *vstart = S->h_vstart.as<double>();
-    mdp_vi_stats *hf = S->h_fstat.as<mdp_vi_stats>();
     for (int i = 0; i < n; ++i) {
       ServeReq *r = ret[i];
       const size_t ns = (size_t)r->z.ns;
@@ -2716,25 +2708,76 @@ mdp_status mdp_server_step(mdp_server *S, void *stream, int32_t *n_active)
           (r->h_v && (e = hipMemcpyAsync(r->h_v, r->v, 8 * ns, hipMemcpyDeviceToHost, s)) != hipSuccess))
         return hip_fail(S->ctx, e, "serve results");
     }
-    if ((e = hipMemcpyAsync(hf, S->d_vstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = serve_wait(S, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(S->h_fstat.p, S->d_vstat, sizeof(mdp_vi_stats) * n, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipEventRecord(S->ret_ev, s)) != hipSuccess)
       return hip_fail(S->ctx, e, "serve retire");
-    for (int i = 0; i < n; ++i) {
-      ServeReq *r = ret[i];
-      r->res.sweeps = hf[i].sweeps;
-      r->res.residual = hf[i].residual;
-      r->res.v_start = vstart[i];
-      r->res.status = r->res.build_status != MDP_OK ? r->res.build_status : hf[i].status;
-      r->res.done_step = S->step_no;
-      S->done.push_back(r->res);
-      unreserve(S, r);
-      delete r;
-    }
+    S->retiring.swap(S->to_retire);
   }
-  keep.insert(keep.end(), paused.begin(), paused.end());
-  keep_paused.armed = false;
-  S->running.swap(keep);
-  if (n_active) *n_active = (int32_t)(S->queue.size() + S->n_building() + S->n_solving() + S->running.size());
+  if (S->running.empty() && S->n_building() + S->n_solving() > 0) {  // nothing to sweep until a lane ends
+    if ((rc = poll_lanes(true)) != MDP_OK || (rc = admit_idle()) != MDP_OK) return rc;
+  }
+  if (S->running.empty()) {
+    if (n_active) *n_active = n_act();
+    return MDP_OK;
+  }
+  // ---- sweeps, shortest remaining work first, without starving the oldest:
+  // this step sweeps the built requests whose remaining work (rows times
+  // sweeps still to run) is within kServeWorkRatio of the smallest, and the
+  // earliest-submitted built request in any case; the others wait (their
+  // state is untouched). The step's work is enqueued and the call returns; a
+  // later call reads the status once step_ev has completed.
+  std::vector<ServeReq *> &run = S->step_run;
+  run.clear();
+  {
+    double wmin = 0.0;
+    const ServeReq *oldest = nullptr;
+    for (ServeReq *r : S->running) {
+      const double w = (double)r->z.rows * (r->limit - r->sweeps);
+      if (!oldest || w < wmin) wmin = w;
+      if (!oldest || r->seq < oldest->seq) oldest = r;
+    }
+    for (ServeReq *r : S->running)
+      if (r == oldest || (double)r->z.rows * (r->limit - r->sweeps) <= kServeWorkRatio * wmin) run.push_back(r);
+  }
+  const int n_run = (int)run.size();
+  BatchVIDesc *vd = S->h_vrun.as<BatchVIDesc>();
+  const size_t win = vi_descs(run, vd);
+  if ((e = hipMemcpyAsync(S->d_vrun, vd, sizeof(BatchVIDesc) * n_run, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve solve descriptors");
+  for (int i = 0; i < n_run; ++i) {
+    ServeReq *r = run[i];
+    if (!r->cold) continue;
+    if ((e = launch_vi_reset_batched(S->d_vrun + i, 1, s)) != hipSuccess) return hip_fail(S->ctx, e, "serve reset");
+    r->cold = false;
+  }
+  int k = S->cfg.sweeps_per_step;
+  for (ServeReq *r : run) k = std::min(k, r->limit - r->sweeps);
+  k = std::max(k, 1);
+  std::vector<int> behind(n_run);
+  for (int i = 0; i < n_run; ++i) behind[i] = run[i]->sweeps;
+  std::vector<int64_t> tabs;
+  active_block_tables(vd, behind.data(), n_run, k, tabs);
+  memcpy(S->h_tables.p, tabs.data(), sizeof(int64_t) * tabs.size());
+  if ((e = hipMemcpyAsync(S->d_bs_sweeps, S->h_tables.p, sizeof(int64_t) * tabs.size(), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return hip_fail(S->ctx, e, "serve sweep tables");
+  for (int j = 0; j < k; ++j) {
+    Timed tm(S->ctx, MDP_KERNEL_VI_SWEEP, s);
+    if ((e = launch_vi_sweep_batched(S->d_vrun, n_run, S->d_bs_sweeps + (size_t)j * (n_run + 1), S->d_wg_res,
+                                     kBatchViGrid, win, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve sweep");
+    if ((e = launch_vi_close_batched(S->d_vrun, n_run, kBatchViGrid, S->d_wg_res, S->cfg.tol, s)) != hipSuccess)
+      return hip_fail(S->ctx, e, "serve close");
+  }
+  for (ServeReq *r : run) r->sweeps += k;
+  if ((e = launch_vi_status_batched(S->d_vrun, n_run, S->d_vstat, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(S->h_vstat.p, S->d_vstat, sizeof(mdp_vi_stats) * n_run, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipEventRecord(S->step_ev, s)) != hipSuccess)
+    return hip_fail(S->ctx, e, "serve vi stats");
+  S->step_inflight = true;
+  if (n_active) *n_active = n_act();
   return MDP_OK;
 }
 
@@ -2752,7 +2795,8 @@ mdp_status mdp_server_info(mdp_server *S, mdp_server_state *out)
 {
   if (!S || !out) return MDP_E_INVALID;
   out->queued = (int32_t)S->queue.size();
-  out->in_flight = (int32_t)(S->n_building() + S->n_solving() + S->running.size());
+  out->in_flight =
+      (int32_t)(S->n_building() + S->n_solving() + S->running.size() + S->to_retire.size() + S->retiring.size());
   out->completed = (int32_t)S->done.size();
   out->pad = 0;
   out->pool_used = (int64_t)S->alloc.used();
