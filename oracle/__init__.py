@@ -75,6 +75,8 @@ def load():
         lib.ora_row.restype = C.c_int32
         lib.ora_build.argtypes = [P, E, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp]
         lib.ora_build.restype = C.c_int64
+        lib.ora_build_layers.argtypes = [P, E, C.c_int, C.c_int, vp, vp, vp, C.c_int64, vp, vp, vp, vp, vp]
+        lib.ora_build_layers.restype = C.c_int64
         lib.ora_backward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.ora_jacobi.argtypes = [P, vp, vp, vp, vp, C.c_double, C.c_int32, vp, vp]
         lib.ora_jacobi.restype = C.c_int32
@@ -166,6 +168,39 @@ def build_model(w, cap: int | None = None) -> dict:
         cap = int(nnz)
     return dict(row_ptr=row_ptr, col=col[:nnz].copy(), cnt=cnt[:nnz].copy(), R=R, A=A,
                 row_near=row_near, n_escape=ne.value, n_near_edge=nn.value, nnz=int(nnz))
+
+
+def build_layers(w, t0: int, t1: int) -> dict:
+    """The rows of the decision layers [t0, t1) only (row_ptr local to them, R and A
+    [3][rows of the range]); concatenating the ranges in order gives build_model."""
+    lib = load()
+    b = _Bound(w)
+    rows = (t1 - t0) * w.problem["nx"] * w.problem["ny"] * n_actions(w)
+    cap = max(rows * 4, 1024)
+    while True:
+        row_ptr = np.zeros(rows + 1, np.int64)
+        col = np.zeros(cap, np.int32)
+        cnt = np.zeros(cap, np.int32)
+        R = np.zeros((3, rows))
+        A = np.zeros((3, rows))
+        ne, nn = C.c_int64(0), C.c_int64(0)
+        nnz = lib.ora_build_layers(C.byref(b.p), C.byref(b.e), t0, t1, _ptr(row_ptr), _ptr(col), _ptr(cnt), cap,
+                                   _ptr(R), _ptr(A), None, C.byref(ne), C.byref(nn))
+        if nnz <= cap:
+            break
+        cap = int(nnz)
+    return dict(row_ptr=row_ptr, col=col[:nnz].copy(), cnt=cnt[:nnz].copy(), R=R, A=A, n_escape=ne.value,
+                nnz=int(nnz))
+
+
+def concat_layers(parts: list) -> dict:
+    """One model from build_layers parts of consecutive layer ranges."""
+    offs = np.cumsum([0] + [p["nnz"] for p in parts])
+    row_ptr = np.concatenate([parts[0]["row_ptr"][:1]] + [p["row_ptr"][1:] + o for p, o in zip(parts, offs[:-1])])
+    return dict(row_ptr=row_ptr, col=np.concatenate([p["col"] for p in parts]),
+                cnt=np.concatenate([p["cnt"] for p in parts]), R=np.concatenate([p["R"] for p in parts], axis=1),
+                A=np.concatenate([p["A"] for p in parts], axis=1), n_escape=sum(p["n_escape"] for p in parts),
+                nnz=int(offs[-1]))
 
 
 def backward(w, model: dict, mission: int):

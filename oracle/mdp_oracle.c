@@ -257,22 +257,22 @@ int32_t ora_row(const ora_problem *p, const ora_env *e, int t, int c, int a,
   return n;
 }
 
-int64_t ora_build(const ora_problem *p, const ora_env *e, int64_t *row_ptr, int32_t *col,
-                  int32_t *cnt, int64_t cap, double *R, double *A, int32_t *row_near,
-                  int64_t *n_escape, int64_t *n_near_edge)
+int64_t ora_build_layers(const ora_problem *p, const ora_env *e, int t0, int t1, int64_t *row_ptr,
+                         int32_t *col, int32_t *cnt, int64_t cap, double *R, double *A, int32_t *row_near,
+                         int64_t *n_escape, int64_t *n_near_edge)
 {
   const int nc = p->nx * p->ny, na = n_actions(p);
-  const int64_t rows = (int64_t)p->nt * nc * na;
+  const int64_t rows = (int64_t)(t1 - t0) * nc * na;
   int32_t *tc = (int32_t *)malloc(sizeof(int32_t) * (size_t)p->n_real);
   int32_t *tn = (int32_t *)malloc(sizeof(int32_t) * (size_t)p->n_real);
   int64_t nnz = 0;
   row_ptr[0] = 0;
   *n_escape = 0;
   *n_near_edge = 0;
-  for (int t = 0; t < p->nt; ++t)
+  for (int t = t0; t < t1; ++t)
     for (int c = 0; c < nc; ++c)
       for (int a = 0; a < na; ++a) {
-        const int64_t row = ((int64_t)t * nc + c) * na + a;
+        const int64_t row = ((int64_t)(t - t0) * nc + c) * na + a;
         double Rr[3], Ar[3];
         int64_t near_before = *n_near_edge;
         int32_t n = ora_row(p, e, t, c, a, tc, tn, Rr, Ar, n_escape, n_near_edge);
@@ -291,6 +291,13 @@ int64_t ora_build(const ora_problem *p, const ora_env *e, int64_t *row_ptr, int3
   free(tc);
   free(tn);
   return nnz;
+}
+
+int64_t ora_build(const ora_problem *p, const ora_env *e, int64_t *row_ptr, int32_t *col,
+                  int32_t *cnt, int64_t cap, double *R, double *A, int32_t *row_near,
+                  int64_t *n_escape, int64_t *n_near_edge)
+{
+  return ora_build_layers(p, e, 0, p->nt, row_ptr, col, cnt, cap, R, A, row_near, n_escape, n_near_edge);
 }
 
 /* Q(s, a) = R(s, a) + sum over transient s' of P(s'|s,a) v(s'); both sinks

@@ -75,6 +75,12 @@ int64_t ora_build(const ora_problem *p, const ora_env *e, int64_t *row_ptr, int3
                   int32_t *cnt, int64_t cap, double *R, double *A, int32_t *row_near,
                   int64_t *n_escape, int64_t *n_near_edge);
 
+/* ora_build restricted to the decision layers [t0, t1): row_ptr, R, A and
+ * row_near hold only those layers' rows (row_ptr[0] = 0), in the same order. */
+int64_t ora_build_layers(const ora_problem *p, const ora_env *e, int t0, int t1, int64_t *row_ptr,
+                         int32_t *col, int32_t *cnt, int64_t cap, double *R, double *A, int32_t *row_near,
+                         int64_t *n_escape, int64_t *n_near_edge);
+
 /* Finite-horizon backward induction, t = nt-1 .. 0. R, A are [rows] for one
  * mission; v, w are [nt*nx*ny]; pi [nt*nx*ny]. A and w may be NULL. */
 void ora_backward(const ora_problem *p, const int64_t *row_ptr, const int32_t *col,

@@ -10,11 +10,23 @@ build shape), then checked against the oracle computed one row at a time:
   of the next layer reproduces the GPU's value, and the GPU's action attains
   the oracle's maximum, both within 1e-5 of the state's absolute scale
   max_a E|r| + sum P |v(s')| (the whole oracle backward pass is out of reach
-  at these sizes, so the value test is the Bellman identity at any size)."""
+  at these sizes, so the value test is the Bellman identity at any size);
+- for the paper-shaped instance also the oracle's exact solution at 100
+  sampled states (tests/golden/paper_shaped_values.json, written by
+  tests/golden/make_paper_shaped_values.py from the oracle alone): values
+  within 1e-5 of the absolute-reward value, the GPU policy's action within the
+  same bound of the oracle's maximum Q."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2109_00857_amd import workloads as W
+
+from gpu_helpers import REL_TOL
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +104,22 @@ def test_full_size_sampled(planner, ora, which):
         oracle_rows[int(s)] = [ora.row(w, t, c, a) for a in range(na)]
     # the missions solved together, as the benchmark step does
     vs, vsts = planner.value_iterate_missions(p, model, missions)
+    if which == "paper_shaped":  # against the oracle's exact solution at its sampled states
+        with open(os.path.join(GOLDEN, "paper_shaped_values.json")) as f:
+            g = json.load(f)
+        assert g["nnz"] == st["nnz"]
+        gs = np.array(g["states"])
+        for m, v in zip(missions, vs):
+            o = g["missions"][str(m)]
+            vg = v.cpu().numpy()[gs]
+            v_o, w_o, q_o = np.array(o["v"]), np.array(o["w"]), np.array(o["q"])
+            err = np.abs(vg - v_o)
+            assert np.all(err <= REL_TOL * w_o), (m, gs[err > REL_TOL * w_o][:5])
+            pi = planner.policy(p, model, m, v).cpu().numpy()[gs]
+            qa = q_o[np.arange(len(gs)), pi]
+            assert np.all(qa >= q_o.max(axis=1) - REL_TOL * w_o), m
+            print(f"[full] paper_shaped mission {m}: {len(gs)} states against the oracle's solution, "
+                  f"worst |dv|/w = {float(np.max(err / np.maximum(w_o, 1e-300))):.2e}", flush=True)
     for m, v, vst in zip(missions, vs, vsts):
         assert vst["status"] == 0 and vst["sweeps"] <= nt + 1, vst
         pi = planner.policy(p, model, m, v).cpu().numpy()

@@ -634,3 +634,15 @@ def test_two_speed_corridor_trade_off(ora, case):
     assert abs(v[s0] - c["v_start"]) < 1e-12 and pi[s0] == c["pi_start"], (v[s0], pi[s0])
     best, npol = bruteforce.best_policy_return(m, w.problem, c["mission"])
     assert abs(best - v[s0]) < 1e-12 and npol >= 8
+
+
+def test_build_layers_join_to_the_whole_model(ora):
+    """Models built in consecutive layer ranges and joined equal the whole-domain
+    build row for row (the range build is what the full-size value fixture uses)."""
+    w = W.config2(nx=17, ny=13, nt=6, n_real=300, K=4, n_head=8)
+    full = ora.build_model(w)
+    parts = [ora.build_layers(w, a, b) for a, b in ((0, 2), (2, 3), (3, 6))]
+    joined = ora.concat_layers(parts)
+    assert joined["nnz"] == full["nnz"]
+    for k in ("row_ptr", "col", "cnt", "R", "A"):
+        assert np.array_equal(joined[k], full[k]), k
