@@ -41,13 +41,8 @@ HBM_BW = 8.0e12                        # bytes/s
 MEASURED = {
     ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
                                read=232473807, write=474688784, valu_insts=14415080717),
-    ("k_vi_sweep_missions<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="3d7b9f769a1a050b",
-                                              read=5056668957, write=32613455, valu_insts=499054330),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
                                       read=444055040, write=882345296, valu_insts=13582614500),
-    ("k_vi_sweep_missions<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
-                                                     sha256="3d7b9f769a1a050b", read=416390465, write=14990360,
-                                                     valu_insts=69516916),
 }
 
 
@@ -131,6 +126,15 @@ def _ev_ms(stream, fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+def window_fits(p: dict, na: int) -> bool:
+    """Whether the sweep stages a window of v(t+1) for this problem (and so reads the
+    packed entries): the grid rows a block of min(512 / N_a, N_c) cells reaches,
+    (S - 1) / nx + 2 + 2 h_y of them (at most ny), in 16 KB of fp64."""
+    S = min(512 // na, p["nx"] * p["ny"])
+    rows = min((S - 1) // p["nx"] + 2 + 2 * p["sub_hy"], p["ny"])
+    return rows * p["nx"] * 8 <= 8 * 256 * 8
+
+
 def skipped_fraction(w) -> float:
     """Share of the nominal samples whose source cell is the target or an obstacle
     (their rows are fixed single entries; no landing is computed for them)."""
@@ -174,8 +178,9 @@ W_MISSIONS = {0: "time", 1: "energy", 2: "net_energy"}
 def replan_leg(pl, w, p, env, vs, missions, reps: int = 3) -> dict:
     """Re-planning after a forecast update at the middle layer: new coefficient
     draws for layers t >= nt/2, then mdp_build_from (those layers only) +
-    mdp_value_iterate_layers (those layers only) + mdp_policy, against the full
-    step on the updated environment."""
+    mdp_value_iterate_layers (those layers only, warm-started from the solution
+    before the update) + mdp_policy, against the full step on the updated
+    environment (build, cold solve, policy)."""
     import numpy as np
     import torch
 
@@ -195,9 +200,11 @@ def replan_leg(pl, w, p, env, vs, missions, reps: int = 3) -> dict:
     bst, vst = mdp.stats_buffer(mdp.MdpBuildStats), mdp.stats_buffer(mdp.MdpViStats)
     pi = torch.empty(vs[0].numel(), dtype=torch.int32, device=pl.device)
     s = torch.cuda.current_stream()
-    v = vs[0]
+    v_prev = vs[0].clone()  # the solution before the update: the re-plan's warm start
+    v = torch.empty_like(v_prev)
 
     def replan():
+        v.copy_(v_prev)
         mdp.mdp_build_from(pl.ctx, p, env2, model, t0, scratch, bst, s)
         mdp.mdp_value_iterate_layers(pl.ctx, p, model, m, t0, 1e-6, 100000, v, scratch, vst, s)
         mdp.mdp_policy(pl.ctx, p, model, m, v, pi, s)
@@ -244,7 +251,7 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
     nnz = st0["nnz"]
     del model
     torch.cuda.empty_cache()
-    model = pl.alloc_model(p, nnz)
+    model = pl.alloc_model(p, nnz, packed=True)  # with the fused sweep's packed entries
     scratch = pl.scratch(p)
     vi_scratch = torch.empty(len(missions) * sizes["scratch_bytes"], dtype=torch.uint8, device=pl.device)
     ns = sizes["n_states"]
@@ -310,13 +317,15 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
                       valu_issue_peak_Tops=VALU_LANE_OPS / 1e12)
     # VI (HBM-bound): compulsory bytes of the stored format for the layers each
     # fused sweep recomputes (sweep k of a solve recomputes layers t < nt - k + 1):
-    # per layer 8 B row pointer per row and 6 B per nonzero, read once for all
+    # per layer 8 B row pointer per row and 4 B per nonzero (the packed entry;
+    # 6 B as col + cnt when the problem's window is off), read once for all
     # missions, plus per mission still iterating 4 B reward per row and v read
     # and written once per state.
     nt, nc = p["nt"], p["nx"] * p["ny"]
     rp_layer = model["row_ptr"][:: nc * na].cpu().numpy()  # row_ptr at layer starts (+ end)
     nnz_layer = rp_layer[1:] - rp_layer[:-1]
-    shared_bytes = 8 * nc * na + 6 * nnz_layer
+    packed = window_fits(p, na)
+    shared_bytes = 8 * nc * na + (4 if packed else 6) * nnz_layer
     mission_bytes = 4 * nc * na + 16 * nc
     solve_bytes = 0
     for k in range(max(v["sweeps"] for v in vst)):
@@ -327,9 +336,10 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
     sweep_s = ms_v / 1e3 / n_v
     ach_hbm = solve_bytes * steps / (ms_v / 1e3)
     sweeps_per_step = sum(v["sweeps"] for v in vst)
-    vname = f"k_vi_sweep_missions<{len(missions)}>"
+    vname = f"k_vi_sweep_missions<{len(missions)}, {'true' if packed else 'false'}>"
     roof_vi = dict(bound="hbm", achieved=ach_hbm / 1e9, peak=HBM_BW / 1e9, unit="GB/s", frac=ach_hbm / HBM_BW,
                    traffic=measured_traffic(vname, label), kernel=vname,
+                   bytes_per_nonzero=4 if packed else 6,
                    algorithmic_bytes_per_launch=solve_bytes / max(1, n_v // steps), bytes_full_sweep=sweep_bytes,
                    bytes_per_step=solve_bytes, launch_ms=sweep_s * 1e3)
     out = dict(

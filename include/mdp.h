@@ -108,13 +108,26 @@ typedef struct mdp_env {
  *   col      int32  [nnz_capacity]
  *   cnt      uint16 [nnz_capacity]    realizations landing in col
  *   reward   fp32   [n_missions][N_s*N_a]  one block per set bit of
- *                   mission_mask, in ascending mission order                */
+ *                   mission_mask, in ascending mission order
+ *   ent      uint32 [nnz_capacity], or NULL: the same nonzeros packed for
+ *                   value iteration, (window index << 16) | cnt, where the
+ *                   window index is the column's position in the grid rows of
+ *                   layer t+1 that the sweep stages for the row's block of
+ *                   cells, and 0xFFFF marks DEAD and TARGET. mdp_build and
+ *                   mdp_build_from fill it when it is not NULL and the
+ *                   problem's window fits (rows of (2 sub_hy + 2) grid rows of
+ *                   nx cells in 16 KB; otherwise it is left untouched), and
+ *                   mdp_value_iterate_missions then reads it instead of col
+ *                   and cnt: 4 bytes per nonzero instead of 6, same results
+ *                   bit for bit. Only a model built by mdp_build /
+ *                   mdp_build_from with this ent may be solved with it.    */
 typedef struct mdp_model {
   int64_t *row_ptr;
   int32_t *col;
   uint16_t *cnt;
   float *reward;
   int64_t nnz_capacity;
+  uint32_t *ent;
 } mdp_model;
 
 /* Sizes of a problem (host-only arithmetic, no device work). */

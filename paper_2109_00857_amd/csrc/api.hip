@@ -569,6 +569,8 @@ mdp_status mdp_subgrid_auto(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *e
 static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
                                   void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream,
                                   const Plan &pl, int t_begin = 0);
+static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const Plan &pl, int mission, int n_wg,
+                           VIParams &V);
 
 mdp_status mdp_build(mdp_ctx *ctx, const mdp_problem *p, const mdp_env *env, const mdp_model *model,
                      void *scratch, size_t scratch_bytes, mdp_build_stats *stats, void *stream)
@@ -611,7 +613,8 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
     return MDP_E_INVALID;
   }
   if (!model || !is_device_ptr(model->row_ptr) || !is_device_ptr(model->reward) ||
-      (model->nnz_capacity > 0 && (!is_device_ptr(model->col) || !is_device_ptr(model->cnt)))) {
+      (model->nnz_capacity > 0 && (!is_device_ptr(model->col) || !is_device_ptr(model->cnt))) ||
+      (model->ent && !is_device_ptr(model->ent))) {
     set_err(ctx, "model buffers must be device pointers");
     return MDP_E_INVALID;
   }
@@ -676,6 +679,16 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
       }
     }
   }
+  if (!tiny && model->ent) {  // the fused sweep's packed entries of the rebuilt layers
+    int mission = 0;
+    while (!(p->mission_mask >> mission & 1u)) ++mission;
+    VIParams V;
+    fill_vi_params(p, model, pl, mission, kViGridMaxHost, V);
+    if (V.win_rows > 0) {
+      Timed tm(ctx, MDP_KERNEL_COPY, s);
+      if ((e = launch_compact(V, model->ent, t_begin, s)) != hipSuccess) return hip_fail(ctx, e, "pack");
+    }
+  }
   if ((e = launch_build_finalize(st, model->nnz_capacity, n_slabs, near ? 1 : 0, s)) != hipSuccess)
     return hip_fail(ctx, e, "finalize");
   if ((e = hipMemcpyAsync(stats, &st->out, sizeof(mdp_build_stats), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -721,10 +734,13 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
   V.nc = pl.nc;
   V.nt = p->nt;
   V.hy = p->sub_hy;
+  V.hx = p->sub_hx;
   V.states_per_wg = std::min(kViRows / pl.na, pl.nc);
   V.blocks_per_layer = (pl.nc + V.states_per_wg - 1) / V.states_per_wg;
   V.n_blocks = (int64_t)p->nt * V.blocks_per_layer;
   V.win_rows = vi_window_rows(p->nx, p->ny, p->sub_hy, V.states_per_wg);
+  V.narrow = 4 * (V.states_per_wg + 2 * p->sub_hx) <= p->nx ? 1 : 0;
+  V.ent = V.win_rows > 0 ? model->ent : nullptr;  // packed entries exist only with the window
   V.max_row = pl.max_row;
   V.n_wg = n_wg;
   V.inv_nr = 1.0 / (double)p->n_real;
@@ -906,7 +922,7 @@ static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *
     return MDP_E_INVALID;
   }
   if (!model || !is_device_ptr(model->row_ptr) || !is_device_ptr(model->col) || !is_device_ptr(model->cnt) ||
-      !is_device_ptr(model->reward)) {
+      !is_device_ptr(model->reward) || (model->ent && !is_device_ptr(model->ent))) {
     set_err(ctx, "model buffers must be device pointers");
     return MDP_E_INVALID;
   }

@@ -185,9 +185,11 @@ struct VIParams {
   const int32_t *col;
   const uint16_t *cnt;
   const float *R;           // reward block of the mission
-  int64_t cap;              // length of col / cnt
+  const uint32_t *ent;      // packed entries (window index << 16 | cnt), or nullptr (fused sweep only)
+  int64_t cap;              // length of col / cnt (and ent)
   int64_t ns;
-  int na, nx, ny, nc, nt, hy;
+  int na, nx, ny, nc, nt, hy, hx;
+  int narrow;               // packed entries: blocks inside one grid row stage only the columns they reach
   int states_per_wg;        // S: cells of one layer per block, S * na <= 2 * kBlock rows
   int blocks_per_layer;     // ceil(nc / S)
   int64_t n_blocks;         // nt * blocks_per_layer
@@ -219,6 +221,34 @@ inline int vi_window_rows(int nx, int ny, int hy, int S)
   int rows = (S - 1) / nx + 2 + 2 * hy;
   if (rows > ny) rows = ny;
   return (size_t)rows * nx * 8 <= kViWinBudget ? rows : 0;
+}
+
+// The window of v(t + 1) a block of cells [c0, c0 + nst) of layer t stages:
+// grid rows [j_first - hy, j_last + hy] (clipped) of layer t + 1, whole rows,
+// or with `narrow` and a block inside one grid row only the columns
+// [i_first - hx, i_last + hx] (clipped). Value (row r, column k) of the
+// window sits at r * cols + k; base is the state index of its first value.
+// (The packed entries use narrow windows when the reachable columns are at
+// most a quarter of a grid row, VIParams::narrow; a per-row copy of a few
+// columns costs more than a contiguous copy of whole rows otherwise.)
+struct BlockWin {
+  int64_t base;
+  int rows, cols;
+};
+
+__host__ __device__ inline BlockWin block_window(const VIParams &P, int t, int c0, int nst, bool narrow)
+{
+  const int j0 = c0 / P.nx, j1 = (c0 + nst - 1) / P.nx;
+  const int jw0 = j0 - P.hy > 0 ? j0 - P.hy : 0;
+  const int jw1 = j1 + P.hy < P.ny - 1 ? j1 + P.hy : P.ny - 1;
+  int iw0 = 0, cols = P.nx;
+  if (narrow && j0 == j1) {
+    const int i0 = c0 - j0 * P.nx, i1 = c0 + nst - 1 - j0 * P.nx;
+    iw0 = i0 - P.hx > 0 ? i0 - P.hx : 0;
+    const int iw1 = i1 + P.hx < P.nx - 1 ? i1 + P.hx : P.nx - 1;
+    cols = iw1 - iw0 + 1;
+  }
+  return BlockWin{(int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx + iw0, jw1 - jw0 + 1, cols};
 }
 
 // Layers a sweep recomputes when `sweeps` sweeps of the solve are behind it:
@@ -273,6 +303,10 @@ hipError_t launch_policy_batched(const BatchVIDesc *D, int n, const int64_t *blo
 hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, mdp_vi_stats *dev_stats,
                             hipStream_t s);
 hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s);
+// The packed entries of the fused sweep for layers [t_lo, nt) of a built
+// model (P with win_rows > 0): ent[e] = (window index << 16) | cnt, 0xFFFF for
+// a sink.
+hipError_t launch_compact(const VIParams &P, uint32_t *ent, int t_lo, hipStream_t s);
 
 // Policy rollouts (rollout.hip): one lane per realization.
 struct RollParams {

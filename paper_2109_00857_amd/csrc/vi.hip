@@ -129,7 +129,7 @@ __device__ inline double vi_block(const VIParams &P, const double *vin, double *
   // the window goes straight to LDS (no registers): dword copies, one wave
   // row of 64 dwords per instruction
   {
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const char *src = reinterpret_cast<const char *>(vin + wbase);
     char *dst = reinterpret_cast<char *>(vwin);
     for (int j = wave * 64; j < 2 * wn; j += kBlock) {
@@ -546,7 +546,7 @@ static_assert(mvi_chunk(3) >= kViRows + kViRows / 2 && mvi_chunk(3) <= kViChunk,
 // sweep), Q at the same odd stride and first argmax. Every mission keeps its
 // own rewards, residual, sweep count (buffer parity) and done flag, so its
 // iterates are those of the single-mission sweep bit for bit.
-template <int M>
+template <int M, bool COMPACT>
 __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, int t, int c0, RowSpan span,
                                          double *sm, int win, double *dres)
 {
@@ -578,28 +578,43 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
 #pragma unroll
     for (int h = 0; h < 2; ++h) rr[m][h] = V.d[m].P.R[row0 + min(tid + kBlock * h, nr - 1)];
   }
+  // the block's window of v(t + 1): whole grid rows, or (packed entries,
+  // whose window indices the build computed for this layout) only the
+  // columns a block inside one grid row can reach
   int64_t wbase = 0;
-  int wn = 0;
+  int wn = 0, wcols = P.nx;
   if (P.win_rows > 0 && t + 1 < P.nt) {
-    const int jw0 = max(0, c0 / P.nx - P.hy);
-    const int jw1 = min(P.ny - 1, (c0 + nst - 1) / P.nx + P.hy);
-    wn = (jw1 - jw0 + 1) * P.nx;  // <= win_rows * nx = win
-    wbase = (int64_t)(t + 1) * P.nc + (int64_t)jw0 * P.nx;
+    const BlockWin bw = block_window(P, t, c0, nst, COMPACT && P.narrow);
+    wbase = bw.base;
+    wcols = bw.cols;
+    wn = bw.rows * bw.cols;  // <= win_rows * nx = win
   }
   // each mission's window and own old values go straight to LDS
   double *vwin0 = sm + CHM + 8;       // after the products and the block_max slots
   double *vself0 = vwin0 + M * win;  // [M][S]
   {
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!(live >> m & 1)) continue;  // uniform
       const char *src = reinterpret_cast<const char *>(vin(m) + wbase);
       char *dst = reinterpret_cast<char *>(vwin0 + m * win);
-      for (int j = wave * 64; j < 2 * wn; j += kBlock) {
-        if (j + lane < 2 * wn)
-          __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4,
-                                           0, 0);
+      if (wcols == P.nx) {  // whole rows: one contiguous range
+        for (int j = wave * 64; j < 2 * wn; j += kBlock) {
+          if (j + lane < 2 * wn)
+            __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j),
+                                             4, 0, 0);
+        }
+      } else {  // a few columns of each row: a wave per row
+        const int nrow = wn / wcols;
+        for (int r = wave; r < nrow; r += kBlock / 64) {
+          const char *srow = src + 8 * (size_t)r * P.nx;
+          char *drow = dst + 8 * (size_t)r * wcols;
+          for (int j = 0; j < 2 * wcols; j += 64)
+            if (j + lane < 2 * wcols)
+              __builtin_amdgcn_global_load_lds((gptr_t)(srow + 4 * (size_t)(j + lane)),
+                                               (lptr_t)(drow + 4 * (size_t)j), 4, 0, 0);
+        }
       }
       src = reinterpret_cast<const char *>(vin(m) + s0);
       dst = reinterpret_cast<char *>(vself0 + m * P.states_per_wg);
@@ -610,9 +625,11 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
       }
     }
   }
+  // COMPACT: cc holds the packed entry, (window index << 16) | cnt, 0xFFFF
+  // as the index of a sink
   uint32_t cc[CHM / kBlock];
   uint16_t nn[CHM / kBlock];
-  const uint32_t *colp = P.cap > 0 ? reinterpret_cast<const uint32_t *>(P.col)
+  const uint32_t *colp = P.cap > 0 ? (COMPACT ? P.ent : reinterpret_cast<const uint32_t *>(P.col))
                                    : reinterpret_cast<const uint32_t *>(P.row_ptr);
   const uint16_t *cntp = P.cap > 0 ? P.cnt : reinterpret_cast<const uint16_t *>(P.row_ptr);
   const int64_t elast = max(P.cap - 1, (int64_t)0);
@@ -623,7 +640,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
       const int k = tid + kBlock * j;
       const int64_t e = min(eb + base + (k < ce ? k : 0), elast);
       cc[j] = colp[e];
-      nn[j] = cntp[e];
+      if (!COMPACT) nn[j] = cntp[e];
     }
   };
   load_chunk(0);
@@ -659,14 +676,23 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
         uint32_t outside = 0;
 #pragma unroll
         for (int j = 0; j < kHalf; ++j) {
-          // 32-bit: states and window bases are below 2^31; sinks are never inside
-          const uint32_t w = cc[j0 + j] - wbase32;
-          const bool inw = w < (uint32_t)wn;
-          const double x = vw[inw ? w : 0u];
-          vv[j] = inw ? x : 0.0;
-          outside |= (uint32_t)(!inw && cc[j0 + j] < ns32) << j;
+          if (COMPACT) {  // every state column of a packed model lies in the window
+            uint32_t ej = cc[j0 + j];
+            if (M > 1) asm volatile("" : "+v"(ej));  // decoded per mission: no decoded copies live across missions
+            const uint32_t w = ej >> 16;
+            const bool inw = w != 0xFFFFu;
+            const double x = vw[inw ? w : 0u];
+            vv[j] = inw ? x : 0.0;
+          } else {
+            // 32-bit: states and window bases are below 2^31; sinks are never inside
+            const uint32_t w = cc[j0 + j] - wbase32;
+            const bool inw = w < (uint32_t)wn;
+            const double x = vw[inw ? w : 0u];
+            vv[j] = inw ? x : 0.0;
+            outside |= (uint32_t)(!inw && cc[j0 + j] < ns32) << j;
+          }
         }
-        if (outside) {
+        if (!COMPACT && outside) {
           const double *src = vin(m);
 #pragma unroll
           for (int j = 0; j < kHalf; ++j)
@@ -675,7 +701,17 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
         // slots past the round's entries hold a valid entry; their products
         // land past the rows' ranges and are never summed
 #pragma unroll
-        for (int j = 0; j < kHalf; ++j) prod[tid + kBlock * (j0 + j)] = (double)nn[j0 + j] * vv[j];
+        for (int j = 0; j < kHalf; ++j) {
+          uint32_t n;
+          if (COMPACT) {
+            n = cc[j0 + j];
+            if (M > 1) asm volatile("" : "+v"(n));
+            n &= 0xFFFFu;
+          } else {
+            n = nn[j0 + j];
+          }
+          prod[tid + kBlock * (j0 + j)] = (double)n * vv[j];
+        }
       }
       if (m == M - 1 && top < E) load_chunk(top);  // (mission M - 1 is live: early)
       __syncthreads();
@@ -719,7 +755,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
   __syncthreads();
 }
 
-template <int M>
+template <int M, bool COMPACT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mvi_waves(M), 8))) void k_vi_sweep_missions(
     const MultiVI V, int t_hi, int win, double *wg_res)
 {
@@ -738,7 +774,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mvi_wave
 #pragma unroll
   for (int m = 0; m < M; ++m) d[m] = 0.0;
   for_blocks(V.d[0].P, t_hi, [&](int t, int c0, RowSpan span) {
-    vi_block_missions<M>(V, live, odd, t, c0, span, sm, win, dres);
+    vi_block_missions<M, COMPACT>(V, live, odd, t, c0, span, sm, win, dres);
 #pragma unroll
     for (int m = 0; m < M; ++m) d[m] = fmax(d[m], dres[m]);
   });
@@ -881,18 +917,18 @@ hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *o
   return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool COMPACT>
 static hipError_t sweep_missions_t(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s)
 {
   static bool attr = false;
-  hipError_t e = allow_lds((const void *)k_vi_sweep_missions<M>, attr);
+  hipError_t e = allow_lds((const void *)k_vi_sweep_missions<M, COMPACT>, attr);
   if (e != hipSuccess) return e;
   const VIParams &P = V.d[0].P;
   const int win = P.win_rows * P.nx;
   const size_t lds = ((size_t)mvi_chunk(M) + 8 + (size_t)M * (win + P.states_per_wg)) * 8;
   const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
   const int grid = vi_grid(nb, kViGridMax);
-  hipLaunchKernelGGL(k_vi_sweep_missions<M>, dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
+  hipLaunchKernelGGL((k_vi_sweep_missions<M, COMPACT>), dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_vi_close_missions, dim3(M), dim3(kCloseBlock), 0, s, V, grid, (const double *)wg_res, tol);
   return hipGetLastError();
@@ -900,12 +936,53 @@ static hipError_t sweep_missions_t(const MultiVI &V, int t_hi, double *wg_res, d
 
 hipError_t launch_vi_sweep_missions(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s)
 {
+  const bool packed = V.d[0].P.ent != nullptr && V.d[0].P.win_rows > 0;
   switch (V.m) {
-    case 1: return sweep_missions_t<1>(V, t_hi, wg_res, tol, s);
-    case 2: return sweep_missions_t<2>(V, t_hi, wg_res, tol, s);
-    case 3: return sweep_missions_t<3>(V, t_hi, wg_res, tol, s);
+    case 1: return packed ? sweep_missions_t<1, true>(V, t_hi, wg_res, tol, s)
+                          : sweep_missions_t<1, false>(V, t_hi, wg_res, tol, s);
+    case 2: return packed ? sweep_missions_t<2, true>(V, t_hi, wg_res, tol, s)
+                          : sweep_missions_t<2, false>(V, t_hi, wg_res, tol, s);
+    case 3: return packed ? sweep_missions_t<3, true>(V, t_hi, wg_res, tol, s)
+                          : sweep_missions_t<3, false>(V, t_hi, wg_res, tol, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Packed entries of the blocks of layers [t_lo, nt): one workgroup per block
+// (grid-stride), the window of each block exactly as the fused sweep stages it.
+__global__ __launch_bounds__(kBlock) void k_compact(const VIParams P, uint32_t *ent, int t_lo)
+{
+  const int64_t nb = (int64_t)(P.nt - t_lo) * P.blocks_per_layer;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int t = t_lo + (int)(b / P.blocks_per_layer);
+    const int c0 = (int)(b % P.blocks_per_layer) * P.states_per_wg;
+    const int nst = min(P.states_per_wg, P.nc - c0);
+    const int64_t row0 = ((int64_t)t * P.nc + c0) * P.na;
+    const int64_t eb = min(max(P.row_ptr[row0], (int64_t)0), P.cap);
+    const int64_t ee = min(max(P.row_ptr[row0 + (int64_t)nst * P.na], eb), P.cap);
+    BlockWin bw{0, 0, 1};
+    if (t + 1 < P.nt) bw = block_window(P, t, c0, nst, P.narrow != 0);
+    const int64_t jw0 = (bw.base - (int64_t)(t + 1) * P.nc) / P.nx;
+    const int64_t iw0 = (bw.base - (int64_t)(t + 1) * P.nc) - jw0 * P.nx;
+    for (int64_t e = eb + threadIdx.x; e < ee; e += kBlock) {
+      const int64_t rel = (int64_t)P.col[e] - (int64_t)(t + 1) * P.nc;  // state of layer t+1, or a sink
+      uint32_t code = 0xFFFFu;
+      if (t + 1 < P.nt && rel >= 0 && rel < P.nc) {
+        const int64_t r = rel / P.nx - jw0, k = rel % P.nx - iw0;
+        if (r >= 0 && r < bw.rows && k >= 0 && k < bw.cols) code = (uint32_t)(r * bw.cols + k);
+      }
+      ent[e] = code << 16 | (uint32_t)P.cnt[e];
+    }
+  }
+}
+
+hipError_t launch_compact(const VIParams &P, uint32_t *ent, int t_lo, hipStream_t s)
+{
+  const int64_t nb = (int64_t)std::max(P.nt - t_lo, 0) * P.blocks_per_layer;
+  if (nb == 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(nb, 16384);
+  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(kBlock), 0, s, P, ent, t_lo);
+  return hipGetLastError();
 }
 
 hipError_t launch_vi_finish_missions(const MultiVI &V, mdp_vi_stats *out, hipStream_t s)

@@ -56,7 +56,7 @@ class MdpEnv(C.Structure):
 
 class MdpModel(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("cnt", C.c_void_p),
-                ("reward", C.c_void_p), ("nnz_capacity", C.c_int64)]
+                ("reward", C.c_void_p), ("nnz_capacity", C.c_int64), ("ent", C.c_void_p)]
 
 
 class MdpSizes(C.Structure):
@@ -254,8 +254,7 @@ def mdp_build(ctx, problem: dict, env: dict, model: dict, scratch: torch.Tensor,
               stream=None) -> None:
     """Enqueue the build; `stats` is a (pinned) uint8 host tensor of sizeof(mdp_build_stats)."""
     e = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     rc = load().mdp_build(ctx, C.byref(problem_struct(problem)), C.byref(e), C.byref(m), _ptr(scratch),
                           scratch.numel(), stats.data_ptr(), _stream_handle(stream))
     _check(ctx, rc, "mdp_build")
@@ -265,8 +264,7 @@ def mdp_build_from(ctx, problem: dict, env: dict, model: dict, t0: int, scratch:
                    stream=None) -> None:
     """Enqueue the rebuild of layers [t0, nt) of a built model after the environment changed."""
     e = MdpEnv(*[_ptr(env.get(k)) for k, _ in MdpEnv._fields_])
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     rc = load().mdp_build_from(ctx, C.byref(problem_struct(problem)), C.byref(e), C.byref(m), t0, _ptr(scratch),
                                scratch.numel(), stats.data_ptr(), _stream_handle(stream))
     _check(ctx, rc, "mdp_build_from")
@@ -275,8 +273,7 @@ def mdp_build_from(ctx, problem: dict, env: dict, model: dict, t0: int, scratch:
 def mdp_value_iterate_layers(ctx, problem: dict, model: dict, mission: int, t_first: int, tol: float,
                              max_sweeps: int, v: torch.Tensor, scratch: torch.Tensor, stats: torch.Tensor,
                              stream=None) -> None:
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     rc = load().mdp_value_iterate_layers(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, t_first, tol,
                                          max_sweeps, _ptr(v), _ptr(scratch), scratch.numel(), stats.data_ptr(),
                                          _stream_handle(stream))
@@ -294,8 +291,7 @@ def mdp_build_sync(ctx, stats: torch.Tensor, stream=None) -> int:
 
 def mdp_value_iterate(ctx, problem: dict, model: dict, mission: int, tol: float, max_sweeps: int,
                       v: torch.Tensor, scratch: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     rc = load().mdp_value_iterate(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, tol, max_sweeps,
                                   _ptr(v), _ptr(scratch), scratch.numel(), stats.data_ptr(),
                                   _stream_handle(stream))
@@ -305,8 +301,7 @@ def mdp_value_iterate(ctx, problem: dict, model: dict, mission: int, tol: float,
 def mdp_value_iterate_noalloc(ctx, problem: dict, model: dict, mission: int, tol: float, max_sweeps: int,
                               v: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
     """mdp_value_iterate on the library's static per-GPU scratch (no allocation)."""
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     rc = load().mdp_value_iterate_noalloc(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, tol,
                                           max_sweeps, _ptr(v), stats.data_ptr(), _stream_handle(stream))
     _check(ctx, rc, "mdp_value_iterate_noalloc")
@@ -319,8 +314,7 @@ def mdp_value_iterate_missions(ctx, problem: dict, model: dict, missions, tol: f
                                vs, scratch: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
     """Several missions of one model in one solve; ``stats`` holds len(missions) MdpViStats."""
     n = len(missions)
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     ms = (C.c_int32 * n)(*missions)
     ptrs = (C.c_void_p * n)(*[_ptr(v) for v in vs])
     rc = load().mdp_value_iterate_missions(ctx, C.byref(problem_struct(problem)), C.byref(m), n, ms, tol,
@@ -331,8 +325,7 @@ def mdp_value_iterate_missions(ctx, problem: dict, model: dict, missions, tol: f
 
 def mdp_policy(ctx, problem: dict, model: dict, mission: int, v: torch.Tensor, pi: torch.Tensor,
                stream=None) -> None:
-    m = MdpModel(_ptr(model["row_ptr"]), _ptr(model["col"]), _ptr(model["cnt"]), _ptr(model["reward"]),
-                 int(model["col"].numel()))
+    m = _model_struct(model)
     rc = load().mdp_policy(ctx, C.byref(problem_struct(problem)), C.byref(m), mission, _ptr(v), _ptr(pi),
                            _stream_handle(stream))
     _check(ctx, rc, "mdp_policy")
@@ -409,22 +402,29 @@ class Planner:
         env["mask"] = None if w.mask is None else torch.from_numpy(w.mask).to(d)
         return env
 
-    def alloc_model(self, problem: dict, capacity: int) -> dict:
+    def alloc_model(self, problem: dict, capacity: int, packed: bool = False) -> dict:
+        """Model buffers for `capacity` nonzeros; with `packed`, also the fused sweep's
+        packed entries (mdp_build fills them)."""
         sz = mdp_build_query(problem)
         d = self.device
-        return dict(
+        m = dict(
             row_ptr=torch.empty(sz["n_rows"] + 1, dtype=torch.int64, device=d),
             col=torch.empty(max(capacity, 1), dtype=torch.int32, device=d),
             cnt=torch.empty(max(capacity, 1), dtype=torch.uint16, device=d),
             reward=torch.empty((sz["n_missions"], sz["n_rows"]), dtype=torch.float32, device=d),
         )
+        if packed:
+            m["ent"] = torch.empty(max(capacity, 1), dtype=torch.int32, device=d)
+        return m
 
     def scratch(self, problem: dict) -> torch.Tensor:
         sz = mdp_build_query(problem)
         return torch.empty(sz["scratch_bytes"], dtype=torch.uint8, device=self.device)
 
-    def build(self, problem: dict, env: dict, capacity: int | None = None, scratch=None, stream=None):
+    def build(self, problem: dict, env: dict, capacity: int | None = None, scratch=None, stream=None,
+              packed: bool = True):
         """Build with a capacity guess; rebuild once with the exact nnz if it was too small.
+        With `packed` the model also holds the fused sweep's packed entries.
         Returns (model, stats). Synchronises the stream."""
         sz = mdp_build_query(problem)
         if capacity is None:
@@ -432,7 +432,7 @@ class Planner:
         if scratch is None:
             scratch = self.scratch(problem)
         for _ in range(2):
-            model = self.alloc_model(problem, capacity)
+            model = self.alloc_model(problem, capacity, packed)
             st = stats_buffer(MdpBuildStats)
             mdp_build(self.ctx, problem, env, model, scratch, st, stream)
             mdp_build_sync(self.ctx, st, stream)
@@ -441,8 +441,9 @@ class Planner:
                 break
             capacity = stats["nnz"]
         if stats["status"] == MDP_OK:
-            model["col"] = model["col"][: stats["nnz"]]
-            model["cnt"] = model["cnt"][: stats["nnz"]]
+            for k in ("col", "cnt", "ent"):
+                if k in model:
+                    model[k] = model[k][: stats["nnz"]]
         return model, stats
 
     def value_iterate(self, problem: dict, model: dict, mission: int, tol: float = 1e-6,
@@ -498,7 +499,9 @@ class Planner:
 
 # ---------------------------------------------------------------- batches
 def _model_struct(m: dict) -> MdpModel:
-    return MdpModel(_ptr(m["row_ptr"]), _ptr(m["col"]), _ptr(m["cnt"]), _ptr(m["reward"]), int(m["col"].numel()))
+    """The C view of a model dict; "ent" (the fused sweep's packed entries) is optional."""
+    return MdpModel(_ptr(m["row_ptr"]), _ptr(m["col"]), _ptr(m["cnt"]), _ptr(m["reward"]), int(m["col"].numel()),
+                    _ptr(m.get("ent")))
 
 
 def mdp_batch_query(problems: list, pool_entries: int = 0) -> int:

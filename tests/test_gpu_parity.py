@@ -254,6 +254,59 @@ def test_vi_missions_fused_equals_single(planner, ora):
         assert_values_close(vs[i].cpu().numpy(), v_ora, w_ora)
 
 
+@pytest.mark.parametrize("shape", ["whole_rows", "narrow"])
+def test_packed_entries(planner, ora, shape):
+    """The build's packed entries for the fused sweep: each nonzero's
+    (window index << 16) | count, the index taken in the grid rows of layer t+1
+    that the sweep stages for the block of cells holding the row (0xFFFF for
+    DEAD and TARGET, and every state column lies inside its window; a block
+    inside one grid row stages only the columns it can reach, others whole
+    rows); the fused solve reads them and gives the same values as from col /
+    cnt, bit for bit. Blocks of 32 cells straddle some of the 37-cell rows."""
+    import torch
+
+    if shape == "whole_rows":  # 32-cell blocks against 37-cell rows: whole-row windows
+        w = W.config2(nx=37, ny=29, nt=5, n_real=600)
+    else:  # 16-cell blocks (32 headings) in 150-cell rows: narrow windows
+        w = W.config2(nx=150, ny=12, nt=4, n_real=300, K=4, n_head=32)
+    p = w.problem
+    model, st = planner.build(p, planner.upload_env(w))
+    assert st["status"] == 0 and "ent" in model
+    nnz = st["nnz"]
+    rp = model["row_ptr"].cpu().numpy()
+    col = model["col"][:nnz].cpu().numpy().astype(np.int64)
+    cnt = model["cnt"][:nnz].cpu().numpy().astype(np.int64)
+    ent = model["ent"][:nnz].cpu().numpy().view(np.uint32).astype(np.int64)
+    nx, ny, nt, hx, hy = p["nx"], p["ny"], p["nt"], p["sub_hx"], p["sub_hy"]
+    nc, na, ns = nx * ny, w.n_actions, w.n_states
+    S = min(512 // na, nc)
+    row = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    t, c = divmod(row // na, nc)
+    c0 = c // S * S
+    nst = np.minimum(S, nc - c0)
+    j0, j1 = c0 // nx, (c0 + nst - 1) // nx
+    jw0 = np.maximum(0, j0 - hy)
+    rows = np.minimum(ny - 1, j1 + hy) - jw0 + 1
+    # a block inside one grid row stages only the columns it can reach, when
+    # those are at most a quarter of a row
+    one_row = (j0 == j1) & (4 * (S + 2 * hx) <= nx)
+    iw0 = np.where(one_row, np.maximum(0, c0 - j0 * nx - hx), 0)
+    cols = np.where(one_row, np.minimum(nx - 1, c0 + nst - 1 - j0 * nx + hx) - iw0 + 1, nx)
+    jj, ii = divmod(col - (t + 1) * nc, nx)
+    r, k = jj - jw0, ii - iw0
+    inside = (t + 1 < nt) & (col < ns) & (r >= 0) & (r < rows) & (k >= 0) & (k < cols)
+    assert np.all(inside | (col >= ns)), "a state column outside its window"
+    assert one_row.any() == (4 * (S + 2 * hx) <= nx) and not one_row.all()
+    code = np.where(inside, r * cols + k, 0xFFFF)
+    np.testing.assert_array_equal(ent, code << 16 | cnt)
+    unpacked = {k: v for k, v in model.items() if k != "ent"}
+    vs, sts = planner.value_iterate_missions(p, model, w.missions())
+    vu, stu = planner.value_iterate_missions(p, unpacked, w.missions())
+    assert sts == stu
+    for a, b in zip(vs, vu):
+        assert torch.equal(a, b)
+
+
 def test_vi_missions_rejects_bad_arguments(planner):
     """Argument errors of the fused solve come back synchronously as MDP_E_INVALID
     (or MDP_E_SCRATCH) and enqueue nothing."""

@@ -51,7 +51,7 @@ def test_build_from_equals_full_rebuild(planner, ora, t0):
     print(f"[replan] t0={t0}", flush=True)
     ref, ref_st = planner.build(p, env2)  # full build on the new environment
     assert ref_st["status"] == 0
-    old = planner.alloc_model(p, ref_st["nnz"] + 5000)  # room for the rebuilt model
+    old = planner.alloc_model(p, ref_st["nnz"] + 5000, packed=True)  # room for the rebuilt model
     scratch = planner.scratch(p)
     st = mdp.stats_buffer(mdp.MdpBuildStats)
     mdp.mdp_build(planner.ctx, p, env, old, scratch, st)
@@ -66,6 +66,7 @@ def test_build_from_equals_full_rebuild(planner, ora, t0):
     assert s["samples"] < ref_st["samples"] and s["samples"] <= rows_rebuilt * p["n_real"]
     assert _same(old["row_ptr"], ref["row_ptr"]) and _same(old["reward"], ref["reward"])
     assert _same(old["col"][:nnz], ref["col"][:nnz]) and _same(old["cnt"][:nnz], ref["cnt"][:nnz])
+    assert _same(old["ent"][:nnz], ref["ent"][:nnz])  # the fused sweep's packed entries too
     # and the rebuilt model is the oracle's model of the new environment
     om = ora.build_model(w2)
     g = model_to_host(old, s)
