@@ -43,6 +43,12 @@ MEASURED = {
                                read=232473807, write=474688784, valu_insts=14415080717),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
                                       read=444055040, write=882345296, valu_insts=13582614500),
+    ("k_vi_sweep_missions<1, true>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
+                                                    sha256="c7b54f53c852f0f9", read=3941071378, write=32608730,
+                                                    valu_insts=387264624),
+    ("k_vi_sweep_missions<3, true>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
+                                                           sha256="c7b54f53c852f0f9", read=353441047,
+                                                           write=14990360, valu_insts=66518069),
 }
 
 
