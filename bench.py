@@ -367,6 +367,13 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
         out["rollouts"] = rollout_leg(pl, w, p, env, pis, missions)
         if len(missions) == 1:
             out["replan"] = replan_leg(pl, w, p, env, vs, missions)
+        if not near_edge:  # the build with near-edge counting on (untimed in the step)
+            pn = dict(p, flags=p["flags"] | mdp.MDP_FLAG_NEAR_EDGE)
+            ms_near = _ev_ms(stream, lambda: mdp.mdp_build(pl.ctx, pn, env, model, scratch, bstat, stream), 2)
+            bn = mdp.read_stats(bstat, mdp.MdpBuildStats)
+            assert bn["status"] == mdp.MDP_OK, bn
+            out["build_near_edge"] = dict(ms=ms_near, ms_without=build_s * 1e3, n_near_edge=bn["n_near_edge"],
+                                          near_edge_fraction=bn["n_near_edge"] / max(bn["samples"], 1))
     del model, scratch, vi_scratch, vs, pis
     torch.cuda.empty_cache()
     return out
@@ -685,7 +692,7 @@ def main():
         "roofline": rf[main_leg["dominant"]],
         "rooflines": rf,
     }
-    for k in ("rollouts", "replan"):
+    for k in ("rollouts", "replan", "build_near_edge"):
         if k in main_leg:
             out[k] = main_leg[k]
     if not args.no_second:
