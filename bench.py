@@ -43,10 +43,10 @@ MEASURED = {
                                read=232473807, write=474688784, valu_insts=14415080717),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
                                       read=444055040, write=882345296, valu_insts=13582614500),
-    ("k_vi_sweep_missions<1, true>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
+    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
                                                     sha256="c7b54f53c852f0f9", read=3941071378, write=32608730,
                                                     valu_insts=387264624),
-    ("k_vi_sweep_missions<3, true>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
+    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
                                                            sha256="c7b54f53c852f0f9", read=353441047,
                                                            write=14990360, valu_insts=66518069),
 }
@@ -139,6 +139,16 @@ def window_fits(p: dict, na: int) -> bool:
     S = min(512 // na, p["nx"] * p["ny"])
     rows = min((S - 1) // p["nx"] + 2 + 2 * p["sub_hy"], p["ny"])
     return rows * p["nx"] * 8 <= 8 * 256 * 8
+
+
+def packs(p: dict, na: int) -> bool:
+    """Whether the build packs the model for the fused sweep: the window fits and the
+    entries of a sweep block (min(512 / N_a, N_c) cells, their N_a rows of at most
+    max_row entries: the sub-grid's cells, one more with the swept-path test, at most
+    n_real) have 16-bit offsets."""
+    nsg = (2 * p["sub_hx"] + 1) * (2 * p["sub_hy"] + 1) + (1 if p.get("flags", 0) & 2 else 0)
+    S = min(512 // na, p["nx"] * p["ny"])
+    return window_fits(p, na) and S * na * min(nsg, p["n_real"]) <= 0xFFFF
 
 
 def skipped_fraction(w) -> float:
@@ -323,15 +333,15 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
                       valu_issue_peak_Tops=VALU_LANE_OPS / 1e12)
     # VI (HBM-bound): compulsory bytes of the stored format for the layers each
     # fused sweep recomputes (sweep k of a solve recomputes layers t < nt - k + 1):
-    # per layer 8 B row pointer per row and 4 B per nonzero (the packed entry;
-    # 6 B as col + cnt when the problem's window is off), read once for all
+    # per layer 2 B row offset per row and 4 B per nonzero (the packed model;
+    # 8 B row pointer and 6 B as col + cnt when it is not packed), read once for all
     # missions, plus per mission still iterating 4 B reward per row and v read
     # and written once per state.
     nt, nc = p["nt"], p["nx"] * p["ny"]
     rp_layer = model["row_ptr"][:: nc * na].cpu().numpy()  # row_ptr at layer starts (+ end)
     nnz_layer = rp_layer[1:] - rp_layer[:-1]
-    packed = window_fits(p, na)
-    shared_bytes = 8 * nc * na + (4 if packed else 6) * nnz_layer
+    packed = packs(p, na)
+    shared_bytes = (2 if packed else 8) * nc * na + (4 if packed else 6) * nnz_layer
     mission_bytes = 4 * nc * na + 16 * nc
     solve_bytes = 0
     for k in range(max(v["sweeps"] for v in vst)):
@@ -342,7 +352,7 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
     sweep_s = ms_v / 1e3 / n_v
     ach_hbm = solve_bytes * steps / (ms_v / 1e3)
     sweeps_per_step = sum(v["sweeps"] for v in vst)
-    vname = f"k_vi_sweep_missions<{len(missions)}, {'true' if packed else 'false'}>"
+    vname = f"k_vi_sweep_rows<{len(missions)}>" if packed else f"k_vi_sweep_missions<{len(missions)}>"
     roof_vi = dict(bound="hbm", achieved=ach_hbm / 1e9, peak=HBM_BW / 1e9, unit="GB/s", frac=ach_hbm / HBM_BW,
                    traffic=measured_traffic(vname, label), kernel=vname,
                    bytes_per_nonzero=4 if packed else 6,

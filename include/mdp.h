@@ -120,7 +120,18 @@ typedef struct mdp_env {
  *                   mdp_value_iterate_missions then reads it instead of col
  *                   and cnt: 4 bytes per nonzero instead of 6, same results
  *                   bit for bit. Only a model built by mdp_build /
- *                   mdp_build_from with this ent may be solved with it.    */
+ *                   mdp_build_from with this ent may be solved with it.
+ *   roff     uint16 [N_s*N_a], NULL exactly when ent is NULL: each row's
+ *                   first entry relative to the first entry of its sweep
+ *                   block (B = min(512 / N_a, N_x N_y) consecutive cells of
+ *                   one layer, all their actions), written with ent; the
+ *                   packed sweep reads it instead of row_ptr (2 bytes per row
+ *                   instead of 8). Packing also needs every block's entries
+ *                   to fit 16 bits: B * N_a * max_row <= 65535, max_row =
+ *                   min(sub-grid cells, plus one with MDP_FLAG_SWEPT_PATH,
+ *                   n_real); otherwise ent and roff are left untouched and
+ *                   unused. ent and roff are both NULL or both set
+ *                   (MDP_E_INVALID otherwise).                             */
 typedef struct mdp_model {
   int64_t *row_ptr;
   int32_t *col;
@@ -128,6 +139,7 @@ typedef struct mdp_model {
   float *reward;
   int64_t nnz_capacity;
   uint32_t *ent;
+  uint16_t *roff;
 } mdp_model;
 
 /* Sizes of a problem (host-only arithmetic, no device work). */

@@ -614,8 +614,12 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
   }
   if (!model || !is_device_ptr(model->row_ptr) || !is_device_ptr(model->reward) ||
       (model->nnz_capacity > 0 && (!is_device_ptr(model->col) || !is_device_ptr(model->cnt))) ||
-      (model->ent && !is_device_ptr(model->ent))) {
+      (model->ent && !is_device_ptr(model->ent)) || (model->roff && !is_device_ptr(model->roff))) {
     set_err(ctx, "model buffers must be device pointers");
+    return MDP_E_INVALID;
+  }
+  if ((model->ent == nullptr) != (model->roff == nullptr)) {
+    set_err(ctx, "ent and roff go together");
     return MDP_E_INVALID;
   }
   if (!stats) {
@@ -684,9 +688,9 @@ static mdp_status build_with_plan(mdp_ctx *ctx, const mdp_problem *p, const mdp_
     while (!(p->mission_mask >> mission & 1u)) ++mission;
     VIParams V;
     fill_vi_params(p, model, pl, mission, kViGridMaxHost, V);
-    if (V.win_rows > 0) {
+    if (V.ent) {
       Timed tm(ctx, MDP_KERNEL_COPY, s);
-      if ((e = launch_compact(V, model->ent, t_begin, s)) != hipSuccess) return hip_fail(ctx, e, "pack");
+      if ((e = launch_compact(V, model->ent, model->roff, t_begin, s)) != hipSuccess) return hip_fail(ctx, e, "pack");
     }
   }
   if ((e = launch_build_finalize(st, model->nnz_capacity, n_slabs, near ? 1 : 0, s)) != hipSuccess)
@@ -740,7 +744,11 @@ static void fill_vi_params(const mdp_problem *p, const mdp_model *model, const P
   V.n_blocks = (int64_t)p->nt * V.blocks_per_layer;
   V.win_rows = vi_window_rows(p->nx, p->ny, p->sub_hy, V.states_per_wg);
   V.narrow = 4 * (V.states_per_wg + 2 * p->sub_hx) <= p->nx ? 1 : 0;
-  V.ent = V.win_rows > 0 ? model->ent : nullptr;  // packed entries exist only with the window
+  // packed entries exist only with the window, and with every block's entries
+  // addressable by 16-bit row offsets
+  const bool offs16 = (int64_t)V.states_per_wg * pl.na * pl.max_row <= 0xFFFF;
+  V.ent = (V.win_rows > 0 && offs16) ? model->ent : nullptr;
+  V.roff = V.ent ? model->roff : nullptr;
   V.max_row = pl.max_row;
   V.n_wg = n_wg;
   V.inv_nr = 1.0 / (double)p->n_real;
@@ -922,8 +930,13 @@ static mdp_status vi_setup(mdp_ctx *ctx, const mdp_problem *p, const mdp_model *
     return MDP_E_INVALID;
   }
   if (!model || !is_device_ptr(model->row_ptr) || !is_device_ptr(model->col) || !is_device_ptr(model->cnt) ||
-      !is_device_ptr(model->reward) || (model->ent && !is_device_ptr(model->ent))) {
+      !is_device_ptr(model->reward) || (model->ent && !is_device_ptr(model->ent)) ||
+      (model->roff && !is_device_ptr(model->roff))) {
     set_err(ctx, "model buffers must be device pointers");
+    return MDP_E_INVALID;
+  }
+  if ((model->ent == nullptr) != (model->roff == nullptr)) {
+    set_err(ctx, "ent and roff go together");
     return MDP_E_INVALID;
   }
   fill_vi_params(p, model, pl, mission, kViGridMaxHost, V);

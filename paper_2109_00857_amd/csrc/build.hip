@@ -192,12 +192,18 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   // are zero, so their fma(0, phi, u) terms return u exactly and the landing
   // arithmetic is the K-term sum; loads are clamped to mode K-1 and to the last
   // realization (every load in bounds) instead of branching.
+  // K is KMAX or KMAX - 1 (the kernel is compiled for even mode bounds), so
+  // only the last slot can be a zero term. Each mode's row is a uniform base
+  // address plus the lane's 32-bit offset: no per-mode vector address
+  // arithmetic.
+  const bool last_mode = P.K == KMAX;
   auto load_mu = [&](int r0, float *m) {
-    const int r = min(r0 + rlane, P.nr - 1);
+    const uint32_t rb = 4u * (uint32_t)min(r0 + rlane, P.nr - 1);  // byte offset of the lane's realization
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-      const float val = mu_t[(size_t)min(k, P.K - 1) * P.nr + r];
-      m[k] = (k < P.K) ? val : 0.0f;
+      const char *mk = reinterpret_cast<const char *>(mu_t + (size_t)(k < KMAX - 1 ? k : P.K - 1) * P.nr);
+      const float val = *reinterpret_cast<const float *>(mk + rb);
+      m[k] = (k < KMAX - 1 || last_mode) ? val : 0.0f;
     }
   };
   float m[KMAX];  // coefficients of the current chunk

@@ -186,6 +186,7 @@ struct VIParams {
   const uint16_t *cnt;
   const float *R;           // reward block of the mission
   const uint32_t *ent;      // packed entries (window index << 16 | cnt), or nullptr (fused sweep only)
+  const uint16_t *roff;     // with ent: each row's first entry relative to its block's first entry
   int64_t cap;              // length of col / cnt (and ent)
   int64_t ns;
   int na, nx, ny, nc, nt, hy, hx;
@@ -305,8 +306,8 @@ hipError_t launch_vi_finish(const VIParams &P, double *v, const double *v_alt, m
 hipError_t launch_policy(const VIParams &P, const double *v, int32_t *pi, hipStream_t s);
 // The packed entries of the fused sweep for layers [t_lo, nt) of a built
 // model (P with win_rows > 0): ent[e] = (window index << 16) | cnt, 0xFFFF for
-// a sink.
-hipError_t launch_compact(const VIParams &P, uint32_t *ent, int t_lo, hipStream_t s);
+// a sink, and roff[row] = row_ptr[row] - row_ptr[first row of the row's block].
+hipError_t launch_compact(const VIParams &P, uint32_t *ent, uint16_t *roff, int t_lo, hipStream_t s);
 
 // Policy rollouts (rollout.hip): one lane per realization.
 struct RollParams {

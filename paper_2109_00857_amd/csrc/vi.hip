@@ -539,14 +539,15 @@ __global__ __launch_bounds__(kBlock) void k_policy_batched(const BatchVIDesc *D,
 constexpr int mvi_chunk(int M) { return M == 3 ? 768 : 1024; }
 constexpr int mvi_waves(int M) { return M == 3 ? 7 : (M == 2 ? 6 : 7); }  // per SIMD, the occupancy aimed at
 static_assert(mvi_chunk(3) >= kViRows + kViRows / 2 && mvi_chunk(3) <= kViChunk, "fused chunk size");
-// Several missions of one model in one sweep. A block's row offsets and
-// entries are read from HBM once, into registers; the missions that have not
+// Several missions of one model in one sweep (models without packed entries;
+// packed ones take the row sweep below). A block's row offsets and entries
+// are read from HBM once, into registers; the missions that have not
 // converged then take turns over them, each with its own window of v_old(t + 1)
 // (copied to LDS at the start), products, row sums (ascending, as in the single
 // sweep), Q at the same odd stride and first argmax. Every mission keeps its
 // own rewards, residual, sweep count (buffer parity) and done flag, so its
 // iterates are those of the single-mission sweep bit for bit.
-template <int M, bool COMPACT>
+template <int M>
 __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, int t, int c0, RowSpan span,
                                          double *sm, int win, double *dres)
 {
@@ -578,15 +579,12 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
 #pragma unroll
     for (int h = 0; h < 2; ++h) rr[m][h] = V.d[m].P.R[row0 + min(tid + kBlock * h, nr - 1)];
   }
-  // the block's window of v(t + 1): whole grid rows, or (packed entries,
-  // whose window indices the build computed for this layout) only the
-  // columns a block inside one grid row can reach
+  // the block's window of v(t + 1): whole grid rows
   int64_t wbase = 0;
-  int wn = 0, wcols = P.nx;
+  int wn = 0;
   if (P.win_rows > 0 && t + 1 < P.nt) {
-    const BlockWin bw = block_window(P, t, c0, nst, COMPACT && P.narrow);
+    const BlockWin bw = block_window(P, t, c0, nst, false);
     wbase = bw.base;
-    wcols = bw.cols;
     wn = bw.rows * bw.cols;  // <= win_rows * nx = win
   }
   // each mission's window and own old values go straight to LDS
@@ -599,22 +597,10 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
       if (!(live >> m & 1)) continue;  // uniform
       const char *src = reinterpret_cast<const char *>(vin(m) + wbase);
       char *dst = reinterpret_cast<char *>(vwin0 + m * win);
-      if (wcols == P.nx) {  // whole rows: one contiguous range
-        for (int j = wave * 64; j < 2 * wn; j += kBlock) {
-          if (j + lane < 2 * wn)
-            __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j),
-                                             4, 0, 0);
-        }
-      } else {  // a few columns of each row: a wave per row
-        const int nrow = wn / wcols;
-        for (int r = wave; r < nrow; r += kBlock / 64) {
-          const char *srow = src + 8 * (size_t)r * P.nx;
-          char *drow = dst + 8 * (size_t)r * wcols;
-          for (int j = 0; j < 2 * wcols; j += 64)
-            if (j + lane < 2 * wcols)
-              __builtin_amdgcn_global_load_lds((gptr_t)(srow + 4 * (size_t)(j + lane)),
-                                               (lptr_t)(drow + 4 * (size_t)j), 4, 0, 0);
-        }
+      for (int j = wave * 64; j < 2 * wn; j += kBlock) {  // whole rows: one contiguous range
+        if (j + lane < 2 * wn)
+          __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4,
+                                           0, 0);
       }
       src = reinterpret_cast<const char *>(vin(m) + s0);
       dst = reinterpret_cast<char *>(vself0 + m * P.states_per_wg);
@@ -625,12 +611,10 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
       }
     }
   }
-  // COMPACT: cc holds the packed entry, (window index << 16) | cnt, 0xFFFF
-  // as the index of a sink
   uint32_t cc[CHM / kBlock];
   uint16_t nn[CHM / kBlock];
-  const uint32_t *colp = P.cap > 0 ? (COMPACT ? P.ent : reinterpret_cast<const uint32_t *>(P.col))
-                                   : reinterpret_cast<const uint32_t *>(P.row_ptr);
+  const uint32_t *colp =
+      P.cap > 0 ? reinterpret_cast<const uint32_t *>(P.col) : reinterpret_cast<const uint32_t *>(P.row_ptr);
   const uint16_t *cntp = P.cap > 0 ? P.cnt : reinterpret_cast<const uint16_t *>(P.row_ptr);
   const int64_t elast = max(P.cap - 1, (int64_t)0);
   auto load_chunk = [&](int base) {
@@ -640,7 +624,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
       const int k = tid + kBlock * j;
       const int64_t e = min(eb + base + (k < ce ? k : 0), elast);
       cc[j] = colp[e];
-      if (!COMPACT) nn[j] = cntp[e];
+      nn[j] = cntp[e];
     }
   };
   load_chunk(0);
@@ -676,23 +660,14 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
         uint32_t outside = 0;
 #pragma unroll
         for (int j = 0; j < kHalf; ++j) {
-          if (COMPACT) {  // every state column of a packed model lies in the window
-            uint32_t ej = cc[j0 + j];
-            if (M > 1) asm volatile("" : "+v"(ej));  // decoded per mission: no decoded copies live across missions
-            const uint32_t w = ej >> 16;
-            const bool inw = w != 0xFFFFu;
-            const double x = vw[inw ? w : 0u];
-            vv[j] = inw ? x : 0.0;
-          } else {
-            // 32-bit: states and window bases are below 2^31; sinks are never inside
-            const uint32_t w = cc[j0 + j] - wbase32;
-            const bool inw = w < (uint32_t)wn;
-            const double x = vw[inw ? w : 0u];
-            vv[j] = inw ? x : 0.0;
-            outside |= (uint32_t)(!inw && cc[j0 + j] < ns32) << j;
-          }
+          // 32-bit: states and window bases are below 2^31; sinks are never inside
+          const uint32_t w = cc[j0 + j] - wbase32;
+          const bool inw = w < (uint32_t)wn;
+          const double x = vw[inw ? w : 0u];
+          vv[j] = inw ? x : 0.0;
+          outside |= (uint32_t)(!inw && cc[j0 + j] < ns32) << j;
         }
-        if (!COMPACT && outside) {
+        if (outside) {
           const double *src = vin(m);
 #pragma unroll
           for (int j = 0; j < kHalf; ++j)
@@ -702,15 +677,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
         // land past the rows' ranges and are never summed
 #pragma unroll
         for (int j = 0; j < kHalf; ++j) {
-          uint32_t n;
-          if (COMPACT) {
-            n = cc[j0 + j];
-            if (M > 1) asm volatile("" : "+v"(n));
-            n &= 0xFFFFu;
-          } else {
-            n = nn[j0 + j];
-          }
-          prod[tid + kBlock * (j0 + j)] = (double)n * vv[j];
+          prod[tid + kBlock * (j0 + j)] = (double)nn[j0 + j] * vv[j];
         }
       }
       if (m == M - 1 && top < E) load_chunk(top);  // (mission M - 1 is live: early)
@@ -755,7 +722,7 @@ __device__ inline void vi_block_missions(const MultiVI &V, int live, int odd, in
   __syncthreads();
 }
 
-template <int M, bool COMPACT>
+template <int M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mvi_waves(M), 8))) void k_vi_sweep_missions(
     const MultiVI V, int t_hi, int win, double *wg_res)
 {
@@ -774,13 +741,240 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mvi_wave
 #pragma unroll
   for (int m = 0; m < M; ++m) d[m] = 0.0;
   for_blocks(V.d[0].P, t_hi, [&](int t, int c0, RowSpan span) {
-    vi_block_missions<M, COMPACT>(V, live, odd, t, c0, span, sm, win, dres);
+    vi_block_missions<M>(V, live, odd, t, c0, span, sm, win, dres);
 #pragma unroll
     for (int m = 0; m < M; ++m) d[m] = fmax(d[m], dres[m]);
   });
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const double mx = block_max(d[m], sm + mvi_chunk(M));
+    if (threadIdx.x == 0) wg_res[(int64_t)blockIdx.x * M + m] = mx;
+  }
+}
+
+// ------------------------------------------------------------------ packed rows
+// The fused sweep over a packed model, one thread per row: the thread loads
+// its rows' packed entries itself (the row offsets of a block are read while
+// the previous block is swept), so a block waits on memory once: its entries,
+// rewards, window and own-value copies are all in flight together. Each row
+// sums count x v(window index) in ascending entry order from 0, as the staged
+// sweep does, so the values are those of the single-mission sweep bit for bit.
+constexpr int kRowUnroll = 8;      // entries of a row loaded at once; longer rows load the rest in passes
+constexpr int kRowQ = kViRows + kViRows / 2;  // Q of the block's rows at the odd stride
+constexpr uint32_t kNoOff = 0xFFFFu;          // no offset: a row past the block (as a start: none; as an end: E)
+
+// Offsets of this thread's two rows (tid, tid + kBlock) of the block of cells
+// [c0, c0 + nst) of layer t: start | end << 16, kNoOff past the block.
+__device__ inline void load_row_offsets(const VIParams &P, int t, int c0, uint32_t (&orow)[2])
+{
+  const int nst = min(P.states_per_wg, P.nc - c0);
+  const int nr = nst * P.na;
+  const int64_t row0 = ((int64_t)t * P.nc + c0) * P.na;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = threadIdx.x + kBlock * h;
+    const uint32_t o0 = r < nr ? (uint32_t)P.roff[row0 + r] : kNoOff;
+    const uint32_t o1 = r + 1 < nr ? (uint32_t)P.roff[row0 + r + 1] : kNoOff;
+    orow[h] = o0 | o1 << 16;
+  }
+}
+
+template <int M, typename Prefetch>
+__device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t, int c0, RowSpan span,
+                                     const uint32_t (&orow)[2], Prefetch &&prefetch, double *sm, int win,
+                                     double *dres)
+{
+  const VIParams &P = V.d[0].P;
+  double *qbuf = sm;  // Q of one mission at a time
+  const int tid = threadIdx.x;
+  const int nst = min(P.states_per_wg, P.nc - c0);
+  const int nr = nst * P.na;
+  const int64_t s0 = (int64_t)t * P.nc + c0;
+  const int64_t row0 = s0 * P.na;
+  auto vin = [&](int m) -> const double * { return (odd >> m & 1) ? V.d[m].v_alt : V.d[m].v; };
+  auto vout = [&](int m) -> double * { return (odd >> m & 1) ? V.d[m].v : V.d[m].v_alt; };
+  const int64_t eb = min(max(span.rb, (int64_t)0), P.cap);
+  const int64_t ee = min(min(max(span.re, eb), P.cap), eb + (int64_t)nr * P.max_row);
+  const int E = (int)(ee - eb);
+  const int64_t elast = max(P.cap - 1, (int64_t)0);
+  // ---- this thread's rows and their first entries
+  int lo[2], len[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t o0 = orow[h] & 0xFFFFu, o1 = orow[h] >> 16;
+    lo[h] = o0 == kNoOff ? E : min((int)o0, E);
+    const int hi = o1 == kNoOff ? E : min((int)o1, E);
+    len[h] = max(hi - lo[h], 0);
+  }
+  uint32_t ent[2][kRowUnroll];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int j = 0; j < kRowUnroll; ++j) {
+      ent[h][j] = kNoOff << 16;  // a sink with count 0 where the row has no entry j
+      if (j < len[h]) ent[h][j] = P.ent[min(eb + lo[h] + j, elast)];
+    }
+  }
+  float rr[M][2];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rr[m][h] = V.d[m].P.R[row0 + min(tid + kBlock * h, nr - 1)];
+  }
+  // ---- each mission's window of v(t + 1) and own old values, straight to LDS
+  int64_t wbase = 0;
+  int wn = 0, wcols = P.nx;
+  if (t + 1 < P.nt) {
+    const BlockWin bw = block_window(P, t, c0, nst, P.narrow != 0);
+    wbase = bw.base;
+    wcols = bw.cols;
+    wn = bw.rows * bw.cols;  // <= win_rows * nx = win
+  }
+  double *vwin0 = sm + kRowQ + 8;    // after Q and the block_max slots
+  double *vself0 = vwin0 + M * win;  // [M][S]
+  {
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!(live >> m & 1)) continue;  // uniform
+      const char *src = reinterpret_cast<const char *>(vin(m) + wbase);
+      char *dst = reinterpret_cast<char *>(vwin0 + m * win);
+      if (wcols == P.nx) {  // whole rows: one contiguous range
+        for (int j = wave * 64; j < 2 * wn; j += kBlock) {
+          if (j + lane < 2 * wn)
+            __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j),
+                                             4, 0, 0);
+        }
+      } else {  // a few columns of each row: a wave per row
+        const int nrow = wn / wcols;
+        for (int r = wave; r < nrow; r += kBlock / 64) {
+          const char *srow = src + 8 * (size_t)r * P.nx;
+          char *drow = dst + 8 * (size_t)r * wcols;
+          for (int j = 0; j < 2 * wcols; j += 64)
+            if (j + lane < 2 * wcols)
+              __builtin_amdgcn_global_load_lds((gptr_t)(srow + 4 * (size_t)(j + lane)),
+                                               (lptr_t)(drow + 4 * (size_t)j), 4, 0, 0);
+        }
+      }
+      src = reinterpret_cast<const char *>(vin(m) + s0);
+      dst = reinterpret_cast<char *>(vself0 + m * P.states_per_wg);
+      for (int j = wave * 64; j < 2 * nst; j += kBlock) {
+        if (j + lane < 2 * nst)
+          __builtin_amdgcn_global_load_lds((gptr_t)(src + 4 * (size_t)(j + lane)), (lptr_t)(dst + 4 * (size_t)j), 4,
+                                           0, 0);
+      }
+    }
+  }
+  prefetch();  // the next block's row offsets
+  wait_vm();   // entries, rewards, this wave's copies (and the prefetch, in flight alongside)
+  __syncthreads();  // every wave's copies
+  const int qstride = P.na | 1;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    dres[m] = 0.0;
+    if (!(live >> m & 1)) continue;
+    const double *vw = vwin0 + m * win;
+    double acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      acc[h] = 0.0;
+#pragma unroll
+      for (int j = 0; j < kRowUnroll; ++j) {
+        uint32_t e = ent[h][j];
+        if (M > 1) asm volatile("" : "+v"(e));  // decoded per mission
+        if ((e & 0xFFFFu) != 0u) {  // an entry of the row (every entry counts at least one landing)
+          const uint32_t w = e >> 16;
+          const double x = w != kNoOff ? vw[w] : 0.0;
+          acc[h] += (double)(e & 0xFFFFu) * x;
+        }
+      }
+      for (int k = kRowUnroll; k < len[h]; ++k) {  // the rest of a long row
+        const uint32_t e = P.ent[min(eb + lo[h] + k, elast)];
+        const uint32_t w = e >> 16;
+        const double x = w != kNoOff ? vw[w] : 0.0;
+        acc[h] += (double)(e & 0xFFFFu) * x;
+      }
+    }
+    __syncthreads();  // the previous readers of qbuf
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = tid + kBlock * h;
+      if (r < nr) qbuf[r + (qstride - P.na) * (r / P.na)] = (double)rr[m][h] + acc[h] * V.d[m].P.inv_nr;
+    }
+    __syncthreads();
+    if (tid < nst) {
+      int besta;
+      const double best = first_max(qbuf + tid * qstride, P.na, besta);
+      vout(m)[s0 + tid] = best;
+      dres[m] = fabs(best - vself0[m * P.states_per_wg + tid]);
+    }
+  }
+  wait_vm();  // no copy into LDS outlives the block
+  __syncthreads();
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(M == 1 ? 8 : 7, 8))) void k_vi_sweep_rows(
+    const MultiVI V, int t_hi, int win, double *wg_res)
+{
+  extern __shared__ double sm[];
+  int live = 0, odd = 0;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const VIState *st = V.d[m].st;
+    live |= (st->done == 0) << m;
+    odd |= (st->sweeps & 1) << m;
+  }
+  live = __builtin_amdgcn_readfirstlane(live);
+  odd = __builtin_amdgcn_readfirstlane(odd);
+  if (!live) return;  // every mission has converged
+  double d[M], dres[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) d[m] = 0.0;
+  // the blocks of this workgroup, as for_blocks walks them, with the next
+  // block's row offsets loaded during the current block
+  const VIParams &P = V.d[0].P;
+  const int bpl = P.blocks_per_layer;
+  const int t_lo = min(P.t_lo, t_hi);
+  const int b0 = t_lo * bpl;
+  const int nb = (t_hi - t_lo) * bpl;
+  const int x = (int)blockIdx.x % kXcds, nslot = (int)gridDim.x / kXcds;
+  const int b_end = b0 + (int)((int64_t)nb * (x + 1) / kXcds);
+  int b = b0 + (int)((int64_t)nb * x / kXcds) + (int)blockIdx.x / kXcds;
+  if (b < b_end) {
+    const int gq = nslot / bpl, gr = nslot % bpl;
+    int t = b / bpl, c = b - t * bpl;
+    RowSpan span = block_span(P, t, c * P.states_per_wg);
+    uint32_t orow[2];
+    load_row_offsets(P, t, c * P.states_per_wg, orow);
+    for (; b < b_end; b += nslot) {
+      int tn = t + gq, cn = c + gr;
+      if (cn >= bpl) {
+        cn -= bpl;
+        ++tn;
+      }
+      const bool more = (int64_t)b + nslot < b_end;
+      RowSpan nxt{0, 0};
+      if (more) nxt = block_span(P, tn, cn * P.states_per_wg);
+      uint32_t onext[2] = {kNoOff | kNoOff << 16, kNoOff | kNoOff << 16};
+      vi_block_rows<M>(
+          V, live, odd, t, c * P.states_per_wg, span, orow,
+          [&] {
+            if (more) load_row_offsets(P, tn, cn * P.states_per_wg, onext);
+          },
+          sm, win, dres);
+#pragma unroll
+      for (int m = 0; m < M; ++m) d[m] = fmax(d[m], dres[m]);
+      t = tn;
+      c = cn;
+      span = nxt;
+      orow[0] = onext[0];
+      orow[1] = onext[1];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double mx = block_max(d[m], sm + kRowQ);
     if (threadIdx.x == 0) wg_res[(int64_t)blockIdx.x * M + m] = mx;
   }
 }
@@ -917,18 +1111,35 @@ hipError_t launch_vi_status_batched(const BatchVIDesc *D, int n, mdp_vi_stats *o
   return hipGetLastError();
 }
 
-template <int M, bool COMPACT>
+template <int M>
+static hipError_t sweep_rows_t(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s)
+{
+  static bool attr = false;
+  hipError_t e = allow_lds((const void *)k_vi_sweep_rows<M>, attr);
+  if (e != hipSuccess) return e;
+  const VIParams &P = V.d[0].P;
+  const int win = P.win_rows * P.nx;
+  const size_t lds = ((size_t)kRowQ + 8 + (size_t)M * (win + P.states_per_wg)) * 8;
+  const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
+  const int grid = vi_grid(nb, kViGridMax);
+  hipLaunchKernelGGL(k_vi_sweep_rows<M>, dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vi_close_missions, dim3(M), dim3(kCloseBlock), 0, s, V, grid, (const double *)wg_res, tol);
+  return hipGetLastError();
+}
+
+template <int M>
 static hipError_t sweep_missions_t(const MultiVI &V, int t_hi, double *wg_res, double tol, hipStream_t s)
 {
   static bool attr = false;
-  hipError_t e = allow_lds((const void *)k_vi_sweep_missions<M, COMPACT>, attr);
+  hipError_t e = allow_lds((const void *)k_vi_sweep_missions<M>, attr);
   if (e != hipSuccess) return e;
   const VIParams &P = V.d[0].P;
   const int win = P.win_rows * P.nx;
   const size_t lds = ((size_t)mvi_chunk(M) + 8 + (size_t)M * (win + P.states_per_wg)) * 8;
   const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
   const int grid = vi_grid(nb, kViGridMax);
-  hipLaunchKernelGGL((k_vi_sweep_missions<M, COMPACT>), dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
+  hipLaunchKernelGGL((k_vi_sweep_missions<M>), dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_vi_close_missions, dim3(M), dim3(kCloseBlock), 0, s, V, grid, (const double *)wg_res, tol);
   return hipGetLastError();
@@ -938,19 +1149,16 @@ hipError_t launch_vi_sweep_missions(const MultiVI &V, int t_hi, double *wg_res, 
 {
   const bool packed = V.d[0].P.ent != nullptr && V.d[0].P.win_rows > 0;
   switch (V.m) {
-    case 1: return packed ? sweep_missions_t<1, true>(V, t_hi, wg_res, tol, s)
-                          : sweep_missions_t<1, false>(V, t_hi, wg_res, tol, s);
-    case 2: return packed ? sweep_missions_t<2, true>(V, t_hi, wg_res, tol, s)
-                          : sweep_missions_t<2, false>(V, t_hi, wg_res, tol, s);
-    case 3: return packed ? sweep_missions_t<3, true>(V, t_hi, wg_res, tol, s)
-                          : sweep_missions_t<3, false>(V, t_hi, wg_res, tol, s);
+    case 1: return packed ? sweep_rows_t<1>(V, t_hi, wg_res, tol, s) : sweep_missions_t<1>(V, t_hi, wg_res, tol, s);
+    case 2: return packed ? sweep_rows_t<2>(V, t_hi, wg_res, tol, s) : sweep_missions_t<2>(V, t_hi, wg_res, tol, s);
+    case 3: return packed ? sweep_rows_t<3>(V, t_hi, wg_res, tol, s) : sweep_missions_t<3>(V, t_hi, wg_res, tol, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // Packed entries of the blocks of layers [t_lo, nt): one workgroup per block
 // (grid-stride), the window of each block exactly as the fused sweep stages it.
-__global__ __launch_bounds__(kBlock) void k_compact(const VIParams P, uint32_t *ent, int t_lo)
+__global__ __launch_bounds__(kBlock) void k_compact(const VIParams P, uint32_t *ent, uint16_t *roff, int t_lo)
 {
   const int64_t nb = (int64_t)(P.nt - t_lo) * P.blocks_per_layer;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -973,15 +1181,17 @@ __global__ __launch_bounds__(kBlock) void k_compact(const VIParams P, uint32_t *
       }
       ent[e] = code << 16 | (uint32_t)P.cnt[e];
     }
+    const int64_t rb = P.row_ptr[row0];  // the block's first entry (offsets below 2^16 by the host's check)
+    for (int r = threadIdx.x; r < nst * P.na; r += kBlock) roff[row0 + r] = (uint16_t)(P.row_ptr[row0 + r] - rb);
   }
 }
 
-hipError_t launch_compact(const VIParams &P, uint32_t *ent, int t_lo, hipStream_t s)
+hipError_t launch_compact(const VIParams &P, uint32_t *ent, uint16_t *roff, int t_lo, hipStream_t s)
 {
   const int64_t nb = (int64_t)std::max(P.nt - t_lo, 0) * P.blocks_per_layer;
   if (nb == 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>(nb, 16384);
-  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(kBlock), 0, s, P, ent, t_lo);
+  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(kBlock), 0, s, P, ent, roff, t_lo);
   return hipGetLastError();
 }
 

@@ -56,7 +56,8 @@ class MdpEnv(C.Structure):
 
 class MdpModel(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("cnt", C.c_void_p),
-                ("reward", C.c_void_p), ("nnz_capacity", C.c_int64), ("ent", C.c_void_p)]
+                ("reward", C.c_void_p), ("nnz_capacity", C.c_int64), ("ent", C.c_void_p),
+                ("roff", C.c_void_p)]
 
 
 class MdpSizes(C.Structure):
@@ -404,7 +405,7 @@ class Planner:
 
     def alloc_model(self, problem: dict, capacity: int, packed: bool = False) -> dict:
         """Model buffers for `capacity` nonzeros; with `packed`, also the fused sweep's
-        packed entries (mdp_build fills them)."""
+        packed entries and row offsets (mdp_build fills them)."""
         sz = mdp_build_query(problem)
         d = self.device
         m = dict(
@@ -415,6 +416,7 @@ class Planner:
         )
         if packed:
             m["ent"] = torch.empty(max(capacity, 1), dtype=torch.int32, device=d)
+            m["roff"] = torch.empty(max(sz["n_rows"], 1), dtype=torch.uint16, device=d)
         return m
 
     def scratch(self, problem: dict) -> torch.Tensor:
@@ -499,9 +501,10 @@ class Planner:
 
 # ---------------------------------------------------------------- batches
 def _model_struct(m: dict) -> MdpModel:
-    """The C view of a model dict; "ent" (the fused sweep's packed entries) is optional."""
+    """The C view of a model dict; "ent" and "roff" (the fused sweep's packed entries
+    and 16-bit row offsets) are optional, together."""
     return MdpModel(_ptr(m["row_ptr"]), _ptr(m["col"]), _ptr(m["cnt"]), _ptr(m["reward"]), int(m["col"].numel()),
-                    _ptr(m.get("ent")))
+                    _ptr(m.get("ent")), _ptr(m.get("roff")))
 
 
 def mdp_batch_query(problems: list, pool_entries: int = 0) -> int:

@@ -261,8 +261,10 @@ def test_packed_entries(planner, ora, shape):
     that the sweep stages for the block of cells holding the row (0xFFFF for
     DEAD and TARGET, and every state column lies inside its window; a block
     inside one grid row stages only the columns it can reach, others whole
-    rows); the fused solve reads them and gives the same values as from col /
-    cnt, bit for bit. Blocks of 32 cells straddle some of the 37-cell rows."""
+    rows), and each row's first entry relative to its block's first entry in
+    16 bits; the fused solve reads them and gives the same values as from
+    row_ptr / col / cnt, bit for bit. Blocks of 32 cells straddle some of the
+    37-cell rows."""
     import torch
 
     if shape == "whole_rows":  # 32-cell blocks against 37-cell rows: whole-row windows
@@ -271,7 +273,7 @@ def test_packed_entries(planner, ora, shape):
         w = W.config2(nx=150, ny=12, nt=4, n_real=300, K=4, n_head=32)
     p = w.problem
     model, st = planner.build(p, planner.upload_env(w))
-    assert st["status"] == 0 and "ent" in model
+    assert st["status"] == 0 and "ent" in model and "roff" in model
     nnz = st["nnz"]
     rp = model["row_ptr"].cpu().numpy()
     col = model["col"][:nnz].cpu().numpy().astype(np.int64)
@@ -299,12 +301,52 @@ def test_packed_entries(planner, ora, shape):
     assert one_row.any() == (4 * (S + 2 * hx) <= nx) and not one_row.all()
     code = np.where(inside, r * cols + k, 0xFFFF)
     np.testing.assert_array_equal(ent, code << 16 | cnt)
-    unpacked = {k: v for k, v in model.items() if k != "ent"}
+    rt, rc = divmod(np.arange(len(rp) - 1) // na, nc)
+    first = (rt * nc + rc // S * S) * na
+    np.testing.assert_array_equal(model["roff"].cpu().numpy().view(np.uint16).astype(np.int64), rp[:-1] - rp[first])
+    unpacked = {k: v for k, v in model.items() if k not in ("ent", "roff")}
     vs, sts = planner.value_iterate_missions(p, model, w.missions())
     vu, stu = planner.value_iterate_missions(p, unpacked, w.missions())
     assert sts == stu
     for a, b in zip(vs, vu):
         assert torch.equal(a, b)
+
+
+def test_blocks_too_large_to_pack(planner):
+    """A 13x13 sub-grid (rows of up to 169 entries) with 400 realizations and 8
+    headings: a sweep block (64 cells x 8 actions) may hold more entries than
+    16-bit offsets reach, so the build leaves the packed buffers untouched and
+    the fused solve reads row_ptr / col / cnt; same values as the unpacked
+    model. ent without roff is refused."""
+    import torch
+
+    from paper_2109_00857_amd import mdp
+
+    w = W.config1(nt=4, n_real=400, sub_h=6)
+    p = w.problem
+    env = planner.upload_env(w)
+    ref, st = planner.build(p, env, packed=False)
+    assert st["status"] == 0
+    model = planner.alloc_model(p, st["nnz"], packed=True)
+    model["ent"].fill_(-1)
+    model["roff"].view(torch.int16).fill_(7)
+    sbuf = mdp.stats_buffer(mdp.MdpBuildStats)
+    scratch = planner.scratch(p)
+    mdp.mdp_build(planner.ctx, p, env, model, scratch, sbuf)
+    assert mdp.mdp_build_sync(planner.ctx, sbuf) == mdp.MDP_OK
+    assert bool((model["ent"] == -1).all()) and bool((model["roff"].view(torch.int16) == 7).all())
+    for k in ("row_ptr", "col", "cnt", "reward"):
+        assert torch.equal(model[k], ref[k]), k
+    vs, sts = planner.value_iterate_missions(p, model, w.missions())
+    vr, str_ = planner.value_iterate_missions(p, ref, w.missions())
+    assert sts == str_ and all(torch.equal(a, b) for a, b in zip(vs, vr))
+    half = {k: v for k, v in model.items() if k != "roff"}
+    with pytest.raises(mdp.MdpError) as e:
+        mdp.mdp_build(planner.ctx, p, env, half, scratch, sbuf)
+    assert e.value.status == mdp.MDP_E_INVALID
+    with pytest.raises(mdp.MdpError) as e:
+        planner.value_iterate_missions(p, half, w.missions())
+    assert e.value.status == mdp.MDP_E_INVALID
 
 
 def test_vi_missions_rejects_bad_arguments(planner):

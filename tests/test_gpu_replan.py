@@ -67,6 +67,7 @@ def test_build_from_equals_full_rebuild(planner, ora, t0):
     assert _same(old["row_ptr"], ref["row_ptr"]) and _same(old["reward"], ref["reward"])
     assert _same(old["col"][:nnz], ref["col"][:nnz]) and _same(old["cnt"][:nnz], ref["cnt"][:nnz])
     assert _same(old["ent"][:nnz], ref["ent"][:nnz])  # the fused sweep's packed entries too
+    assert _same(old["roff"], ref["roff"])
     # and the rebuilt model is the oracle's model of the new environment
     om = ora.build_model(w2)
     g = model_to_host(old, s)
