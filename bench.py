@@ -39,16 +39,14 @@ HBM_BW = 8.0e12                        # bytes/s
 # scaled to bytes by the plain-copy calibration (FETCH x2.000, WRITE x1.000);
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
-    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
-                               read=232473807, write=474688784, valu_insts=14415080717),
-    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="df272314f1bc0d21",
-                                      read=444055040, write=882345296, valu_insts=13582614500),
-    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
-                                                    sha256="c7b54f53c852f0f9", read=3941071378, write=32608730,
-                                                    valu_insts=387264624),
-    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip",
-                                                           sha256="c7b54f53c852f0f9", read=353441047,
-                                                           write=14990360, valu_insts=66518069),
+    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="eb39f7fa6fcad0cd",
+                               read=232388152, write=474691226, valu_insts=12627240717),
+    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="eb39f7fa6fcad0cd",
+                                      read=444074176, write=882336576, valu_insts=12594477052),
+    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="1c4b8e238adbed12",
+                                          read=3150719839, write=32603175, valu_insts=364139130),
+    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="1c4b8e238adbed12",
+                                                 read=294846615, write=14990360, valu_insts=55236062),
 }
 
 
