@@ -305,6 +305,46 @@ float safe_speed(int h, double hmax_abs, double lam, int n)
   return f;
 }
 
+// Pairs of actions for the paired landing loop: actions with bitwise-equal Hx
+// first (headings h and N_h - h, where the rounded tables agree; the x add,
+// floor and column offset of a landing then serve both rows), the remaining
+// actions paired in ascending order. Off (paired = 0) for an odd N_a or when
+// no two actions share Hx.
+static void pair_actions(int na, const float *hx, BuildParams &P)
+{
+  P.paired = 0;
+  P.n_real_pairs = 0;
+  if (na < 2 || (na & 1)) return;
+  bool used[kMaxA] = {};
+  int q = 0;
+  for (int a = 0; a < na; ++a) {
+    if (used[a]) continue;
+    for (int b = a + 1; b < na; ++b)
+      if (!used[b] && memcmp(&hx[a], &hx[b], sizeof(float)) == 0) {
+        used[a] = used[b] = true;
+        P.pair_a[2 * q] = (uint8_t)a;
+        P.pair_a[2 * q + 1] = (uint8_t)b;
+        ++q;
+        break;
+      }
+  }
+  P.n_real_pairs = q;
+  int pending = -1;
+  for (int a = 0; a < na; ++a) {
+    if (used[a]) continue;
+    if (pending < 0) {
+      pending = a;
+    } else {
+      P.pair_a[2 * q] = (uint8_t)pending;
+      P.pair_a[2 * q + 1] = (uint8_t)a;
+      ++q;
+      pending = -1;
+    }
+  }
+  for (int k = 0; k < 2 * q; ++k) P.row_pair[P.pair_a[k]] = (uint8_t)((k >> 1) << 1 | (k & 1));
+  P.paired = P.n_real_pairs > 0 ? 1 : 0;
+}
+
 void fill_params(const mdp_problem *p, const mdp_env *env, const mdp_model *model, const Plan &pl,
                  BuildParams &P, ActionTables &T)
 {
@@ -363,6 +403,7 @@ void fill_params(const mdp_problem *p, const mdp_env *env, const mdp_model *mode
   }
   P.usafe = safe_speed(p->sub_hx, mx, p->dt / p->dx, p->nx);
   P.vsafe = safe_speed(p->sub_hy, my, p->dt / p->dy, p->ny);
+  pair_actions(pl.na, T.hx, P);
 }
 
 // Events bracketing one launch of kernel kind k (no-ops unless profiling).

@@ -122,7 +122,7 @@ struct TileOut {
 
 // One tile of cells at layer t, every action of those cells, every realization.
 // POOL: entries go to a bump-allocated pool slot instead of O.stage.
-template <int KMAX, bool PACK16, bool NEAR, bool POOL, bool SWEPT = false, typename PT>
+template <int KMAX, bool PACK16, bool NEAR, bool POOL, bool SWEPT = false, bool PAIRS = false, typename PT>
 __device__ void build_tile(const PT &P, const int t, const int tile, BuildState *bst,
                            const TileOut &O, uint32_t *lds)
 {
@@ -178,6 +178,38 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
                     (((P.hy - cj) * P.W + (P.hx - ci)) * HW + col_l) * 4;
   const int HW4 = HW * 4;
   const int W = P.W;
+  // The row's counters for the compaction: column row_col, 16-bit half
+  // row_shift (lanes own rows, two rows a word with 16-bit counters).
+  int row_col = col_l;
+  int row_shift = (PACK16 && (tid & HW)) ? 16 : 0;
+  // PAIRS (16-bit counters): in the landing loop a lane owns the two rows of
+  // a pair of actions of one cell, both counters in one word (low: the
+  // pair's first action), and one of kBlock / HW parts of each chunk's
+  // realizations. Pairs whose actions share Hx bitwise come first in every
+  // cell's order and take the lanes [0, cells * n_real): those lanes compute
+  // the x add, floor and column offset once for both rows; the other pairs
+  // take the last lanes (one wave of each part holds them all).
+  const int npc = P.na >> 1, nreal = P.n_real_pairs, npseudo = npc - nreal;
+  auto pair_lane = [&](int cell, int q) {
+    return q < nreal ? cell * nreal + q : P.cells_per_tile * nreal + cell * npseudo + (q - nreal);
+  };
+  int pr_cell = 0, pr_q = 0;
+  if constexpr (PAIRS) {
+    const int rp = P.row_pair[a];
+    row_col = pair_lane(cl, rp >> 1);
+    row_shift = (rp & 1) ? 16 : 0;
+    const int L = tid & (HW - 1);
+    if (L < P.cells_per_tile * nreal) {
+      pr_cell = L / nreal;
+      pr_q = L - pr_cell * nreal;
+    } else if (npseudo > 0) {
+      const int L2 = L - P.cells_per_tile * nreal;
+      pr_cell = L2 / npseudo;
+      pr_q = nreal + (L2 - pr_cell * npseudo);
+    } else {
+      pr_cell = P.cells_per_tile;  // no pair
+    }
+  }
 
   const int rmask = P.rch - 1;
   const int rlane = tid & rmask;
@@ -209,6 +241,30 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   float m[KMAX];  // coefficients of the current chunk
   load_mu(0, m);
   __syncthreads();
+
+  // PAIRS: this lane's pair of rows (the action tables are in LDS now)
+  static_assert(!PAIRS || (PACK16 && !NEAR && !SWEPT), "paired landing loop: 16-bit counters only");
+  bool pr_live = false, pr_real = false;
+  int pr_base4 = 0, pr_part = 0, pr_nparts = 1;
+  float pr_hx1 = 0.0f, pr_hx2 = 0.0f, pr_hy1 = 0.0f, pr_hy2 = 0.0f;
+  const int WHW4 = W * HW4;
+  if constexpr (PAIRS) {
+    pr_part = tid / HW;
+    pr_nparts = kBlock / HW;
+    if (pr_cell < ncell) {
+      const int pc = c0 + pr_cell;
+      const int pci = pc % P.nx, pcj = pc / P.nx;
+      pr_live = !(pci == P.ti && pcj == P.tj) && !(P.mask != nullptr && P.mask[(size_t)t * nc + pc] != 0);
+      const int a1 = P.pair_a[2 * pr_q], a2 = P.pair_a[2 * pr_q + 1];
+      pr_hx1 = tab[a1];
+      pr_hx2 = tab[a2];
+      pr_hy1 = tab[kMaxA + a1];
+      pr_hy2 = tab[kMaxA + a2];
+      pr_real = pr_q < nreal;
+      pr_base4 = (int)__builtin_amdgcn_groupstaticsize() +
+                 (((P.hy - pcj) * W + (P.hx - pci)) * HW + (tid & (HW - 1))) * 4;
+    }
+  }
 
   for (int r0 = 0; r0 < P.nr; r0 += P.rch) {
     const int nloc = min(P.rch, P.nr - r0);
@@ -257,8 +313,67 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
       }
     }
     __syncthreads();
-    // ---------------- phase B: lane = (cell, action) row
-    if (sampled) {
+    // ---------------- phase B: lane = (cell, action) row, or (PAIRS) a pair of rows
+    if constexpr (PAIRS) {
+      if (pr_live) {
+        const float4 *st4 = reinterpret_cast<const float4 *>(stage + pr_cell * sstr);
+        const float2 *st2 = reinterpret_cast<const float2 *>(stage + pr_cell * sstr);
+        const int n4 = nloc >> 2;  // groups of four realizations; this part's share of them
+        const int g0 = n4 * pr_part / pr_nparts, g1 = n4 * (pr_part + 1) / pr_nparts;
+        const bool tail = pr_part == pr_nparts - 1;  // the chunk's last (nloc mod 4) realizations
+        // Both rows of the pair share the x add, floor and column offset when
+        // their Hx agree bitwise; a wave whose pairs all do takes that loop,
+        // the wave holding the other pairs computes both (a uniform branch).
+        const bool wave_shared = __ballot(!pr_real) == 0;
+        // two register sets alternate, the next group loaded before the
+        // current group's counter updates (no prefetch past this part's groups)
+        auto group_loop = [&](auto &&pbin) {
+          auto four = [&](const float4 &X0, const float4 &X1) {
+            pbin(X0.x, X0.y);
+            pbin(X0.z, X0.w);
+            pbin(X1.x, X1.y);
+            pbin(X1.z, X1.w);
+          };
+          int g = g0;
+          if (g < g1) {
+            float4 A0 = st4[2 * g], A1 = st4[2 * g + 1];
+            for (; g + 2 < g1; g += 2) {
+              const float4 B0 = st4[2 * g + 2], B1 = st4[2 * g + 3];
+              four(A0, A1);
+              A0 = st4[2 * g + 4];
+              A1 = st4[2 * g + 5];
+              four(B0, B1);
+            }
+            if (g + 1 < g1) {
+              const float4 B0 = st4[2 * g + 2], B1 = st4[2 * g + 3];
+              four(A0, A1);
+              four(B0, B1);
+            } else {
+              four(A0, A1);
+            }
+          }
+          if (tail)
+            for (int rr = n4 * 4; rr < nloc; ++rr) {
+              const float2 pp = st2[rr];
+              pbin(pp.x, pp.y);
+            }
+        };
+        if (wave_shared) {
+          group_loop([&](float px, float py) {
+            const int xb = mad_i24_s(cvt_floor(px + pr_hx1), HW4, pr_base4);
+            lds_add(mad_i24_s(cvt_floor(py + pr_hy1), WHW4, xb), 1u);
+            lds_add(mad_i24_s(cvt_floor(py + pr_hy2), WHW4, xb), 0x10000u);
+          });
+        } else {
+          group_loop([&](float px, float py) {
+            const int xb = mad_i24_s(cvt_floor(px + pr_hx1), HW4, pr_base4);
+            const int xb2 = mad_i24_s(cvt_floor(px + pr_hx2), HW4, pr_base4);
+            lds_add(mad_i24_s(cvt_floor(py + pr_hy1), WHW4, xb), 1u);
+            lds_add(mad_i24_s(cvt_floor(py + pr_hy2), WHW4, xb2), 0x10000u);
+          });
+        }
+      }
+    } else if (sampled) {
       // Staged positions of this row's cell are read 4 realizations at a time;
       // the next group is loaded before the current group's counter updates.
       const float4 *st4 = reinterpret_cast<const float4 *>(stage + cl * sstr);
@@ -334,7 +449,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   const double F = P.f_max * (double)(jf + 1) / (double)P.n_speed;
   const double e_a = P.c_f * F * F;
   const double g_s = (P.gbar != nullptr && lane_row) ? (double)P.gbar[(size_t)t * nc + c] : 0.0;
-  const int shift = (PACK16 && (tid & HW)) ? 16 : 0;
+  const int shift = row_shift;
 
   uint32_t nnz = 0, dead = 0, tgt = 0, nstate = 0;
   double gsum = 0.0;  // sum over state and target landings of count * gbar(s')
@@ -343,7 +458,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
     for (int dj = -P.hy; dj <= P.hy; ++dj) {
       const int jp = cj + dj;
       for (int di = -P.hx; di <= P.hx; ++di, ++b) {
-        const uint32_t wv = hist[b * HW + col_l];
+        const uint32_t wv = hist[b * HW + row_col];
         const uint32_t n = PACK16 ? ((wv >> shift) & 0xffffu) : wv;
         if (n == 0) continue;
         const int ip = ci + di;
@@ -367,7 +482,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
       }
     }
     if (SWEPT) {  // samples whose path entered an obstacle at t+1
-      const uint32_t wv = hist[P.nsg * HW + col_l];
+      const uint32_t wv = hist[P.nsg * HW + row_col];
       dead += PACK16 ? ((wv >> shift) & 0xffffu) : wv;
     }
     nnz += (dead ? 1u : 0u) + (tgt ? 1u : 0u);
@@ -436,7 +551,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
       for (int dj = -P.hy; dj <= P.hy; ++dj) {
         const int jp = cj + dj;
         for (int di = -P.hx; di <= P.hx; ++di, ++b) {
-          const uint32_t wv = hist[b * HW + col_l];
+          const uint32_t wv = hist[b * HW + row_col];
           const uint32_t n = PACK16 ? ((wv >> shift) & 0xffffu) : wv;
           if (n == 0 || last_layer) continue;
           const int ip = ci + di;
@@ -453,7 +568,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   }
 }
 
-template <int KMAX, bool PACK16, bool NEAR, bool SWEPT>
+template <int KMAX, bool PACK16, bool NEAR, bool SWEPT, bool PAIRS>
 __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const SlabParams S)
 {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -471,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_build(const BuildParams P, const Sla
   O.pool_top = nullptr;
   O.pool_cap = 0;
   O.base_out = nullptr;
-  build_tile<KMAX, PACK16, NEAR, false, SWEPT>(P, t, tile, S.st, O, lds);
+  build_tile<KMAX, PACK16, NEAR, false, SWEPT, PAIRS>(P, t, tile, S.st, O, lds);
 }
 
 // Action displacement tables into device memory (one thread per entry).
@@ -796,10 +911,10 @@ hipError_t launch_build_init_from(BuildState *st, const int64_t *row_ptr_row0, h
   return hipGetLastError();
 }
 
-template <int KMAX, bool PACK16, bool NEAR, bool SWEPT>
+template <int KMAX, bool PACK16, bool NEAR, bool SWEPT, bool PAIRS = false>
 static hipError_t launch_build_t(const BuildParams &P, const SlabParams &S, size_t lds, hipStream_t s)
 {
-  auto kern = k_build<KMAX, PACK16, NEAR, SWEPT>;
+  auto kern = k_build<KMAX, PACK16, NEAR, SWEPT, PAIRS>;
   static bool attr_set = false;  // raise the dynamic-LDS limit once per instantiation
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -816,6 +931,9 @@ template <int KMAX, bool SWEPT>
 static hipError_t launch_build_k(const BuildParams &P, const SlabParams &S, bool pack16, bool near,
                                  size_t lds, hipStream_t s)
 {
+  if constexpr (!SWEPT) {
+    if (pack16 && !near && P.paired) return launch_build_t<KMAX, true, false, false, true>(P, S, lds, s);
+  }
   if (pack16)
     return near ? launch_build_t<KMAX, true, true, SWEPT>(P, S, lds, s)
                 : launch_build_t<KMAX, true, false, SWEPT>(P, S, lds, s);

@@ -42,6 +42,13 @@ struct BuildParams {
   float usafe, vsafe;       // |u| <= usafe and |v| <= vsafe rule out any escape
   double dt, r_term, r_out, c_f, c_r, f_max;
   const float *tab;         // device [2][kMaxA]: Hx then Hy (cell units per step)
+  // Paired landing loop (16-bit counters): the actions form n_pairs = N_a / 2
+  // pairs, the first n_real_pairs of them with bitwise-equal Hx (so both rows
+  // of the pair land in the same column); pair q is actions pair_a[2q] (low
+  // counter half) and pair_a[2q + 1] (high half); row_pair[a] = q << 1 | half.
+  int paired, n_real_pairs;
+  uint8_t pair_a[kMaxA];
+  uint8_t row_pair[kMaxA];
 };
 
 // Host-side action tables, copied to the device by a one-thread-per-entry kernel.
