@@ -909,7 +909,9 @@ __device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t,
       dres[m] = fabs(best - vself0[m * P.states_per_wg + tid]);
     }
   }
-  wait_vm();  // no copy into LDS outlives the block
+  // Every copy into LDS was waited for before the first barrier; what may be
+  // in flight now is the block's value stores, which no later block of this
+  // sweep reads (it reads the other buffer): only the LDS readers must be done.
   __syncthreads();
 }
 
