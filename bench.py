@@ -44,13 +44,13 @@ HBM_BW = 8.0e12                        # bytes/s
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
     ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="3dd6e72964187586",
-                               read=406700553, write=477798443, valu_insts=13480585038),
+                               read=406696318, write=477801787, valu_insts=13480585038),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="3dd6e72964187586",
-                                      read=379614208, write=888014768, valu_insts=13592500565),
-    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="1c4b8e238adbed12",
-                                          read=3150835292, write=32603435, valu_insts=364139130),
-    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="1c4b8e238adbed12",
-                                                 read=294823658, write=14990361, valu_insts=55236062),
+                                      read=378602624, write=888005520, valu_insts=13592500565),
+    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="74dddd8a6a945faa",
+                                          read=3155383714, write=32604713, valu_insts=364139130),
+    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="74dddd8a6a945faa",
+                                                 read=294810638, write=14990361, valu_insts=55236062),
 }
 
 

@@ -397,6 +397,15 @@ def test_wide_grid_without_window(planner, ora):
         assert torch.equal(v, v1), m
 
 
+@pytest.mark.parametrize("n_head", [5, 2])
+def test_unpaired_action_sets(planner, ora, n_head):
+    """Action sets the paired landing loop does not take (an odd N_a; two
+    headings whose x displacements differ): the build keeps one row per lane
+    with 16-bit counters; full parity with the oracle."""
+    w = W.config2(nx=19, ny=17, nt=4, n_real=400, K=4, n_head=n_head, missions=(0, 1))
+    _full_parity(planner, ora, w, f"{n_head} headings")
+
+
 def test_paper_action_set_two_speeds(planner, ora):
     """The paper's application action set, 16 headings x 2 speeds, on config-2
     shapes with all three missions (ragged grid): full parity."""
