@@ -321,7 +321,7 @@ def step_leg(pl, w, label: str, steps: int, warmup: int, autotune: bool = True, 
     # adds of the landing (2) plus the 2K + 2 FMAs (2 flops each) of velocity
     # synthesis and position per (layer, cell, realization), shared by the N_a
     # actions. The measured VALU issue rate (SQ_INSTS_VALU x 64 lanes per launch,
-    # over the live launch time) is reported beside it against 3.93e13 lane-op/s.
+    # over the live launch time) is reported beside it against 7.86e13 lane-op/s.
     flops_per_sample = 2.0 + 2.0 * (2.0 * K + 2.0) / na
     ach_flops = flops_per_sample * samples_launch / build_launch_s
     kname = "k_build"
