@@ -184,28 +184,32 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   int row_shift = (PACK16 && (tid & HW)) ? 16 : 0;
   // PAIRS (16-bit counters): in the landing loop a lane owns the two rows of
   // a pair of actions of one cell, both counters in one word (low: the
-  // pair's first action), and one of kBlock / HW parts of each chunk's
-  // realizations. Pairs whose actions share Hx bitwise come first in every
-  // cell's order and take the lanes [0, cells * n_real): those lanes compute
-  // the x add, floor and column offset once for both rows; the other pairs
-  // take the last lanes (one wave of each part holds them all).
+  // pair's first action; the pair's column: pairs whose actions share Hx
+  // bitwise first, cell by cell, then the others), and one of kBlock / HW
+  // parts of each chunk's realizations. The lanes take (pair, part) jobs with
+  // every part of the shared-Hx pairs first, so whole waves hold only such
+  // pairs and compute the x add, floor and column offset once for both rows;
+  // the jobs of the other pairs take the last lanes.
   const int npc = P.na >> 1, nreal = P.n_real_pairs, npseudo = npc - nreal;
-  auto pair_lane = [&](int cell, int q) {
-    return q < nreal ? cell * nreal + q : P.cells_per_tile * nreal + cell * npseudo + (q - nreal);
-  };
-  int pr_cell = 0, pr_q = 0;
+  const int nrl = P.cells_per_tile * nreal, nps = P.cells_per_tile * npseudo;  // pair columns of each kind
+  auto pair_lane = [&](int cell, int q) { return q < nreal ? cell * nreal + q : nrl + cell * npseudo + (q - nreal); };
+  int pr_cell = 0, pr_q = 0, pr_col = 0, pr_part = 0;
+  const int pr_nparts = kBlock / HW;
   if constexpr (PAIRS) {
     const int rp = P.row_pair[a];
     row_col = pair_lane(cl, rp >> 1);
     row_shift = (rp & 1) ? 16 : 0;
-    const int L = tid & (HW - 1);
-    if (L < P.cells_per_tile * nreal) {
-      pr_cell = L / nreal;
-      pr_q = L - pr_cell * nreal;
-    } else if (npseudo > 0) {
-      const int L2 = L - P.cells_per_tile * nreal;
-      pr_cell = L2 / npseudo;
-      pr_q = nreal + (L2 - pr_cell * npseudo);
+    if (tid < nrl * pr_nparts) {  // a part of a shared-Hx pair
+      pr_col = tid % nrl;
+      pr_part = tid / nrl;
+      pr_cell = pr_col / nreal;
+      pr_q = pr_col - pr_cell * nreal;
+    } else if (tid < (nrl + nps) * pr_nparts) {  // a part of another pair
+      const int j = tid - nrl * pr_nparts;
+      pr_col = nrl + j % nps;
+      pr_part = j / nps;
+      pr_cell = (j % nps) / npseudo;
+      pr_q = nreal + (j % nps) - pr_cell * npseudo;
     } else {
       pr_cell = P.cells_per_tile;  // no pair
     }
@@ -245,12 +249,10 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
   // PAIRS: this lane's pair of rows (the action tables are in LDS now)
   static_assert(!PAIRS || (PACK16 && !NEAR && !SWEPT), "paired landing loop: 16-bit counters only");
   bool pr_live = false, pr_real = false;
-  int pr_base4 = 0, pr_part = 0, pr_nparts = 1;
+  int pr_base4 = 0;
   float pr_hx1 = 0.0f, pr_hx2 = 0.0f, pr_hy1 = 0.0f, pr_hy2 = 0.0f;
   const int WHW4 = W * HW4;
   if constexpr (PAIRS) {
-    pr_part = tid / HW;
-    pr_nparts = kBlock / HW;
     if (pr_cell < ncell) {
       const int pc = c0 + pr_cell;
       const int pci = pc % P.nx, pcj = pc / P.nx;
@@ -261,8 +263,7 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
       pr_hy1 = tab[kMaxA + a1];
       pr_hy2 = tab[kMaxA + a2];
       pr_real = pr_q < nreal;
-      pr_base4 = (int)__builtin_amdgcn_groupstaticsize() +
-                 (((P.hy - pcj) * W + (P.hx - pci)) * HW + (tid & (HW - 1))) * 4;
+      pr_base4 = (int)__builtin_amdgcn_groupstaticsize() + (((P.hy - pcj) * W + (P.hx - pci)) * HW + pr_col) * 4;
     }
   }
 
