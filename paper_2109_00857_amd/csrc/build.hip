@@ -611,35 +611,62 @@ __global__ void k_build_init(BuildState *st, const int64_t *row_ptr_row0)
   }
 }
 
-// Exclusive scan of the per-workgroup entry counts of one pass (one block).
+// Exclusive scan of the per-workgroup entry counts of one pass (one block),
+// in tiles of 1024 x kScanPer counts: read coalesced into LDS, kScanPer
+// consecutive counts per thread, a block scan of the thread sums (lane
+// shuffles within a wave, then the wave totals), the offsets written
+// kScanPer consecutive ones per thread, the running total carried to the
+// next tile.
+constexpr int kScanPer = 8;
 __global__ __launch_bounds__(1024) void k_scan_wg(const uint32_t *wg_nnz, int n, int64_t *wg_off,
                                                   BuildState *st, int64_t *row_ptr_end)
 {
-  __shared__ long long sh[1024];
-  const int tid = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int lo = min(n, tid * per), hi = min(n, lo + per);
-  long long s = 0;
-  for (int k = lo; k < hi; ++k) s += wg_nnz[k];
-  sh[tid] = s;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
-    long long y = (tid >= d) ? sh[tid - d] : 0;
+  __shared__ uint32_t cnt[1024 * kScanPer];
+  __shared__ long long wsum[1024 / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  long long carry = st->running_nnz;
+  for (int base = 0; base < n; base += 1024 * kScanPer) {
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const int k = base + i * 1024 + tid;
+      cnt[i * 1024 + tid] = k < n ? wg_nnz[k] : 0u;
+    }
     __syncthreads();
-    sh[tid] += y;
+    uint32_t v[kScanPer];
+    long long s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      v[j] = cnt[tid * kScanPer + j];
+      s += v[j];
+    }
+    long long x = s;  // inclusive scan of the thread sums within the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const long long y = __shfl_up(x, d, 64);
+      x += lane >= d ? y : 0ll;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
+    long long before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 1024 / 64; ++w) {
+      const long long tw = wsum[w];
+      before += w < wave ? tw : 0ll;
+      total += tw;
+    }
+    long long acc = carry + before + x - s;  // offset of this thread's first count
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      const int k = base + tid * kScanPer + j;
+      if (k < n) wg_off[k] = acc;
+      acc += v[j];
+    }
+    carry += total;
+    __syncthreads();  // the tile's LDS reads before the next tile's writes
   }
-  const long long base = st->running_nnz;
-  long long acc = base + sh[tid] - s;
-  for (int k = lo; k < hi; ++k) {
-    wg_off[k] = acc;
-    acc += wg_nnz[k];
-  }
-  __syncthreads();
-  if (tid == 1023) {
-    const long long tot = base + sh[1023];
-    st->running_nnz = tot;
-    if (row_ptr_end) *row_ptr_end = tot;
+  if (tid == 0) {
+    st->running_nnz = carry;
+    if (row_ptr_end) *row_ptr_end = carry;
   }
 }
 
