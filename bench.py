@@ -43,14 +43,14 @@ HBM_BW = 8.0e12                        # bytes/s
 # scaled to bytes by the plain-copy calibration (FETCH x2.000, WRITE x1.000);
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
-    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="99fc82652f557f07",
-                               read=406700547, write=477815148, valu_insts=11608623532),
-    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="99fc82652f557f07",
-                                      read=377067840, write=888011264, valu_insts=11942296989),
-    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="74dddd8a6a945faa",
-                                          read=3155378103, write=32604991, valu_insts=364139130),
-    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="74dddd8a6a945faa",
-                                                 read=294808639, write=14990360, valu_insts=55236062),
+    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
+                               read=406723540, write=477818844, valu_insts=11608623532),
+    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
+                                      read=377080064, write=888012288, valu_insts=11942296989),
+    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="4fc1a81d79477cf6",
+                                          read=3155285243, write=32604887, valu_insts=364139130),
+    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="4fc1a81d79477cf6",
+                                                 read=294828564, write=14990360, valu_insts=55236062),
 }
 
 

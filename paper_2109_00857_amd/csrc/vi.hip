@@ -1178,7 +1178,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(const VIParams P, uint32_t *
       const int64_t rel = (int64_t)P.col[e] - (int64_t)(t + 1) * P.nc;  // state of layer t+1, or a sink
       uint32_t code = 0xFFFFu;
       if (t + 1 < P.nt && rel >= 0 && rel < P.nc) {
-        const int64_t r = rel / P.nx - jw0, k = rel % P.nx - iw0;
+        const int rj = (int)rel / P.nx;  // a cell of the layer: 32-bit division
+        const int r = rj - (int)jw0, k = (int)rel - rj * P.nx - (int)iw0;
         if (r >= 0 && r < bw.rows && k >= 0 && k < bw.cols) code = (uint32_t)(r * bw.cols + k);
       }
       ent[e] = code << 16 | (uint32_t)P.cnt[e];
