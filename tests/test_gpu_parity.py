@@ -415,6 +415,40 @@ def test_paper_action_set_two_speeds(planner, ora):
     _full_parity(planner, ora, w, "16 headings x 2 speeds")
 
 
+@pytest.mark.parametrize("n_head,n_speed,shapes,loop", [
+    (32, 1, [(256, 256), (128, 256), (64, 128)], "pairs"),
+    (16, 2, [(128, 256), (256, 64)], "pairs"),
+    (8, 1, [(256, 64), (128, 128), (64, 256)], "pairs"),
+    (4, 1, [(256, 64), (64, 128)], "rows"),
+])
+def test_landing_loops_at_every_row_lane_count(planner, ora, n_head, n_speed, shapes, loop):
+    """The paired landing loop (two rows of a pair of actions per lane, 256 / hw
+    realization parts) and the row-per-lane loop at launch shapes with 256, 128
+    and 64 row lanes (2, 4 and 8 parts): every shape's model is the oracle's
+    (counts bit-exact, rewards within the tolerance)."""
+    from paper_2109_00857_amd import mdp
+
+    from gpu_helpers import landing_loop
+
+    w = W.config2(nx=29, ny=23, nt=3, n_real=700, K=4, n_head=n_head, missions=(0, 2))
+    w.problem["n_speed"] = n_speed
+    p = w.problem
+    assert landing_loop(p) == loop
+    om = ora.build_model(w)
+    env = planner.upload_env(w)
+    try:
+        for rl, rch in shapes:
+            print(f"[loops] {n_head}x{n_speed} ({loop}) shape ({rl}, {rch})", flush=True)
+            mdp.mdp_ctx_set_plan(planner.ctx, p, rl, rch, 1)
+            model, st = planner.build(p, env)
+            assert st["status"] == 0 and st["nnz"] == om["nnz"], st
+            g = model_to_host(model, st)
+            assert_counts_equal(g, om)
+            assert_rewards_close(g, om, w.missions())
+    finally:
+        mdp.mdp_ctx_set_plan(planner.ctx, p, 0, 0, 0)
+
+
 @pytest.mark.parametrize("case", [0, 1, 2])
 def test_two_speed_corridor(planner, ora, case):
     """The hand-derived two-speed corridor (slow when the horizon allows, fast
