@@ -22,16 +22,27 @@
 /* Heading h of N_h is the angle 2*pi*h/N_h counter-clockwise from east; speed
  * j of N_F is F_max*(j+1)/N_F; action a = j*N_h + h (Sec. II-A: N_h headings in
  * [0, 2pi) times N_F speeds in (0, F_max]). The displacement a*dt in cell units
- * is evaluated in double and rounded to FP32 once. */
+ * is evaluated in double and rounded to FP32 once. A heading along an axis
+ * (a whole number of quarter turns) has the exact direction components 0 and
+ * +-1, so it moves along that axis only. */
 void ora_action_tables(const ora_problem *p, float *hx, float *hy, double *speed)
 {
   for (int jf = 0; jf < p->n_speed; ++jf) {
     double F = p->f_max * (double)(jf + 1) / (double)p->n_speed;
     for (int h = 0; h < p->n_head; ++h) {
-      double th = 2.0 * ORA_PI * (double)h / (double)p->n_head;
+      double c, s;
+      if ((4 * h) % p->n_head == 0) {
+        const int quarter = (4 * h) / p->n_head;  /* 0..3 */
+        c = quarter == 0 ? 1.0 : (quarter == 2 ? -1.0 : 0.0);
+        s = quarter == 1 ? 1.0 : (quarter == 3 ? -1.0 : 0.0);
+      } else {
+        double th = 2.0 * ORA_PI * (double)h / (double)p->n_head;
+        c = cos(th);
+        s = sin(th);
+      }
       int a = jf * p->n_head + h;
-      if (hx) hx[a] = (float)(F * cos(th) * p->dt / p->dx);
-      if (hy) hy[a] = (float)(F * sin(th) * p->dt / p->dy);
+      if (hx) hx[a] = (float)(F * c * p->dt / p->dx);
+      if (hy) hy[a] = (float)(F * s * p->dt / p->dy);
       if (speed) speed[a] = F;
     }
   }

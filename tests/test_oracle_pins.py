@@ -480,6 +480,30 @@ def test_near_edge_flag_physical_units(ora, axis):
 # ----------------------------------------------------------------------------------------
 # Several speeds: action order a = j*N_h + h, speed F_j = F_max (j+1)/N_F
 # ----------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n_head,n_speed", [(4, 1), (8, 2), (16, 1), (32, 1), (12, 2)])
+def test_axis_headings_move_along_their_axis(ora, n_head, n_speed):
+    """Sec. II-A headings: a heading along an axis (a whole number of quarter
+    turns) has direction components exactly 0 and +-1, so its displacement has
+    an exact zero component and the opposite heading's is its exact negative;
+    every other heading is F (cos, sin) within fp32 rounding."""
+    w = W.uniform_flow(9, 8, 2, 0.1, 0.0, n_real=2, n_head=n_head, f_max=1.3, dx=0.7, dy=0.9, dt=0.5,
+                       start=(0, 0), target=(8, 7), sub_h=3, n_speed=n_speed)
+    hx, hy, sp = ora.action_tables(w)
+    q = n_head // 4
+    for jf in range(n_speed):
+        F = 1.3 * (jf + 1) / n_speed
+        e, n, west, s = (jf * n_head + k * q for k in range(4))
+        assert hy[e] == 0.0 and hy[west] == 0.0 and hx[n] == 0.0 and hx[s] == 0.0
+        assert not (np.signbit(hy[e]) or np.signbit(hy[west]) or np.signbit(hx[n]) or np.signbit(hx[s]))
+        assert hx[e] == np.float32(F * 0.5 / 0.7) and hx[west] == -hx[e]
+        assert hy[n] == np.float32(F * 0.5 / 0.9) and hy[s] == -hy[n]
+        for h in range(n_head):
+            a = jf * n_head + h
+            th = 2 * math.pi * h / n_head
+            assert abs(hx[a] - F * math.cos(th) * 0.5 / 0.7) <= 1e-6 * F
+            assert abs(hy[a] - F * math.sin(th) * 0.5 / 0.9) <= 1e-6 * F
+
+
 def test_two_speeds_zero_coefficients_one_hot(ora):
     """With two speeds and zero coefficients every row is one-hot at the cell of
     x + (vbar + F_j (cos th_h, sin th_h)) dt evaluated in fp64 physical units,
