@@ -276,16 +276,22 @@ bool is_device_ptr(const void *ptr)
 }
 
 // Displacement tables in cell units, evaluated in double and rounded once.
+// Headings along an axis (whole quarter turns) take the exact direction
+// (1, 0), (0, 1), (-1, 0) or (0, -1).
 void action_tables(const mdp_problem *p, float *hx, float *hy)
 {
   const double kPi = 3.14159265358979323846;
+  static const double kAxis[4][2] = {{1.0, 0.0}, {0.0, 1.0}, {-1.0, 0.0}, {0.0, -1.0}};
   for (int jf = 0; jf < p->n_speed; ++jf) {
     const double F = p->f_max * (double)(jf + 1) / (double)p->n_speed;
     for (int h = 0; h < p->n_head; ++h) {
       const double th = 2.0 * kPi * (double)h / (double)p->n_head;
+      const bool axis = (4 * h) % p->n_head == 0;
+      const double dirx = axis ? kAxis[4 * h / p->n_head][0] : cos(th);
+      const double diry = axis ? kAxis[4 * h / p->n_head][1] : sin(th);
       const int a = jf * p->n_head + h;
-      hx[a] = (float)(F * cos(th) * p->dt / p->dx);
-      hy[a] = (float)(F * sin(th) * p->dt / p->dy);
+      hx[a] = (float)(F * dirx * p->dt / p->dx);
+      hy[a] = (float)(F * diry * p->dt / p->dy);
     }
   }
 }
@@ -306,7 +312,8 @@ float safe_speed(int h, double hmax_abs, double lam, int n)
 }
 
 // Pairs of actions for the paired landing loop: actions with bitwise-equal Hx
-// first (headings h and N_h - h, where the rounded tables agree; the x add,
+// first (headings h and N_h - h, where the rounded tables agree, and the axis
+// headings N_h/4 and 3N_h/4, whose Hx are exact zeros; the x add,
 // floor and column offset of a landing then serve both rows), the remaining
 // actions paired in ascending order. Off (paired = 0) for an odd N_a or when
 // no two actions share Hx.

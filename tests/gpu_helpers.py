@@ -86,22 +86,25 @@ def assert_matches_oracle(ora, w, missions, g: dict, stats: dict, values: dict, 
 
 
 
+
+
 def landing_loop(problem: dict) -> str:
     """The landing loop the library takes for a 16-bit-counter build of `problem`,
     by the same rule as its host code: "pairs" when N_a is even and some two
     actions have bitwise-equal fp32 x displacements (each evaluated in double
-    and rounded once), else "rows" (one lane per row). Used to check that the
-    tests cover both loops."""
+    and rounded once, axis headings exact), else "rows" (one lane per row).
+    Used to check that the tests cover both loops."""
     import math
 
     nh, ns = problem["n_head"], problem["n_speed"]
     na = nh * ns
+    if na < 2 or na % 2:
+        return "rows"
+    axis_x = {0: 1.0, 1: 0.0, 2: -1.0, 3: 0.0}
     hx = []
     for jf in range(ns):
         F = problem["f_max"] * (jf + 1) / ns
         for h in range(nh):
-            th = 2.0 * math.pi * h / nh
-            hx.append(np.float32(F * math.cos(th) * problem["dt"] / problem["dx"]).tobytes())
-    if na < 2 or na % 2:
-        return "rows"
+            c = axis_x[4 * h // nh] if (4 * h) % nh == 0 else math.cos(2.0 * math.pi * h / nh)
+            hx.append(np.float32(F * c * problem["dt"] / problem["dx"]).tobytes())
     return "pairs" if len(set(hx)) < na else "rows"

@@ -402,7 +402,10 @@ def test_unpaired_action_sets(planner, ora, n_head):
     """Action sets the paired landing loop does not take (an odd N_a; two
     headings whose x displacements differ): the build keeps one row per lane
     with 16-bit counters; full parity with the oracle."""
+    from gpu_helpers import landing_loop
+
     w = W.config2(nx=19, ny=17, nt=4, n_real=400, K=4, n_head=n_head, missions=(0, 1))
+    assert landing_loop(w.problem) == "rows"
     _full_parity(planner, ora, w, f"{n_head} headings")
 
 
@@ -419,13 +422,15 @@ def test_paper_action_set_two_speeds(planner, ora):
     (32, 1, [(256, 256), (128, 256), (64, 128)], "pairs"),
     (16, 2, [(128, 256), (256, 64)], "pairs"),
     (8, 1, [(256, 64), (128, 128), (64, 256)], "pairs"),
-    (4, 1, [(256, 64), (64, 128)], "rows"),
+    (4, 1, [(256, 64), (64, 128)], "pairs"),
+    (5, 1, [(256, 64), (64, 128)], "rows"),
 ])
 def test_landing_loops_at_every_row_lane_count(planner, ora, n_head, n_speed, shapes, loop):
     """The paired landing loop (two rows of a pair of actions per lane, 256 / hw
-    realization parts) and the row-per-lane loop at launch shapes with 256, 128
-    and 64 row lanes (2, 4 and 8 parts): every shape's model is the oracle's
-    (counts bit-exact, rewards within the tolerance)."""
+    realization parts; waves of pairs sharing Hx and waves holding the other
+    pairs) and the row-per-lane loop at launch shapes with 256, 128 and 64 row
+    lanes (2, 4 and 8 parts): every shape's model is the oracle's (counts
+    bit-exact, rewards within the tolerance)."""
     from paper_2109_00857_amd import mdp
 
     from gpu_helpers import landing_loop
