@@ -44,11 +44,11 @@ HBM_BW = 8.0e12                        # bytes/s
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
     ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                               read=406723540, write=477818844, valu_insts=11608623532),
+                               read=406745194, write=477817579, valu_insts=11608623532),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                                      read=377080064, write=888012288, valu_insts=11942296989),
+                                      read=379996096, write=888015456, valu_insts=11949287382),
     ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="4fc1a81d79477cf6",
-                                          read=3155285243, write=32604887, valu_insts=364139130),
+                                          read=3154923200, write=32604749, valu_insts=364139130),
     ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="4fc1a81d79477cf6",
                                                  read=294828564, write=14990360, valu_insts=55236062),
 }
