@@ -44,13 +44,13 @@ HBM_BW = 8.0e12                        # bytes/s
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
     ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                               read=406745194, write=477817579, valu_insts=11608623532),
+                               read=406577488, write=477810063, valu_insts=11608623532),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                                      read=379996096, write=888015456, valu_insts=11949287382),
-    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="4fc1a81d79477cf6",
-                                          read=3154923200, write=32604749, valu_insts=364139130),
-    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="4fc1a81d79477cf6",
-                                                 read=294828564, write=14990360, valu_insts=55236062),
+                                      read=377146816, write=888010416, valu_insts=11949287382),
+    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="75e7d4a4bd72925e",
+                                          read=3165550183, write=32609907, valu_insts=279657759),
+    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="75e7d4a4bd72925e",
+                                                 read=294775541, write=14990360, valu_insts=50547188),
 }
 
 

@@ -796,7 +796,8 @@ __device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t,
   const int64_t eb = min(max(span.rb, (int64_t)0), P.cap);
   const int64_t ee = min(min(max(span.re, eb), P.cap), eb + (int64_t)nr * P.max_row);
   const int E = (int)(ee - eb);
-  const int64_t elast = max(P.cap - 1, (int64_t)0);
+  // The block's entries [eb, ee): a row's entry j < len lies below ee <= cap.
+  const uint32_t *entb = P.ent + eb;
   // ---- this thread's rows and their first entries
   int lo[2], len[2];
 #pragma unroll
@@ -812,7 +813,7 @@ __device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t,
 #pragma unroll
     for (int j = 0; j < kRowUnroll; ++j) {
       ent[h][j] = kNoOff << 16;  // a sink with count 0 where the row has no entry j
-      if (j < len[h]) ent[h][j] = P.ent[min(eb + lo[h] + j, elast)];
+      if (j < len[h]) ent[h][j] = entb[lo[h] + j];
     }
   }
   float rr[M][2];
@@ -830,15 +831,18 @@ __device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t,
     wcols = bw.cols;
     wn = bw.rows * bw.cols;  // <= win_rows * nx = win
   }
-  double *vwin0 = sm + kRowQ + 8;    // after Q and the block_max slots
-  double *vself0 = vwin0 + M * win;  // [M][S]
+  // [M][win + 1]: each mission's window, then a slot holding 0.0 (set once by
+  // the kernel) that sink entries and a row's missing entries read
+  const int wstride = win + 1;
+  double *vwin0 = sm + kRowQ + 8;        // after Q and the block_max slots
+  double *vself0 = vwin0 + M * wstride;  // [M][S]
   {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!(live >> m & 1)) continue;  // uniform
       const char *src = reinterpret_cast<const char *>(vin(m) + wbase);
-      char *dst = reinterpret_cast<char *>(vwin0 + m * win);
+      char *dst = reinterpret_cast<char *>(vwin0 + m * wstride);
       if (wcols == P.nx) {  // whole rows: one contiguous range
         for (int j = wave * 64; j < 2 * wn; j += kBlock) {
           if (j + lane < 2 * wn)
@@ -873,26 +877,32 @@ __device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t,
   for (int m = 0; m < M; ++m) {
     dres[m] = 0.0;
     if (!(live >> m & 1)) continue;
-    const double *vw = vwin0 + m * win;
+    const double *vw = vwin0 + m * wstride;
+    // count x v(window index), a sink (index kNoOff) or a missing entry (count
+    // 0, index kNoOff) reading the zero slot: acc + 0.0 is acc, and acc, a sum
+    // from +0.0, is never -0.0, so every sum is the skipping sum's bit for bit
+    const uint32_t wz = (uint32_t)win;
     double acc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       acc[h] = 0.0;
+      if constexpr (M == 1) {  // the row's window values read together, then summed
+        double x[kRowUnroll];
 #pragma unroll
-      for (int j = 0; j < kRowUnroll; ++j) {
-        uint32_t e = ent[h][j];
-        if (M > 1) asm volatile("" : "+v"(e));  // decoded per mission
-        if ((e & 0xFFFFu) != 0u) {  // an entry of the row (every entry counts at least one landing)
-          const uint32_t w = e >> 16;
-          const double x = w != kNoOff ? vw[w] : 0.0;
-          acc[h] += (double)(e & 0xFFFFu) * x;
+        for (int j = 0; j < kRowUnroll; ++j) x[j] = vw[min(ent[h][j] >> 16, wz)];
+#pragma unroll
+        for (int j = 0; j < kRowUnroll; ++j) acc[h] += (double)(ent[h][j] & 0xFFFFu) * x[j];
+      } else {  // one at a time (several missions' registers: reading them together spills)
+#pragma unroll
+        for (int j = 0; j < kRowUnroll; ++j) {
+          uint32_t e = ent[h][j];
+          asm volatile("" : "+v"(e));  // decoded per mission
+          acc[h] += (double)(e & 0xFFFFu) * vw[min(e >> 16, wz)];
         }
       }
       for (int k = kRowUnroll; k < len[h]; ++k) {  // the rest of a long row
-        const uint32_t e = P.ent[min(eb + lo[h] + k, elast)];
-        const uint32_t w = e >> 16;
-        const double x = w != kNoOff ? vw[w] : 0.0;
-        acc[h] += (double)(e & 0xFFFFu) * x;
+        const uint32_t e = entb[lo[h] + k];
+        acc[h] += (double)(e & 0xFFFFu) * vw[min(e >> 16, wz)];
       }
     }
     __syncthreads();  // the previous readers of qbuf
@@ -930,6 +940,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(M == 1 ?
   live = __builtin_amdgcn_readfirstlane(live);
   odd = __builtin_amdgcn_readfirstlane(odd);
   if (!live) return;  // every mission has converged
+  // each mission's zero slot after its window (read after a block's first barrier)
+  if (threadIdx.x < M) sm[kRowQ + 8 + threadIdx.x * (win + 1) + win] = 0.0;
   double d[M], dres[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) d[m] = 0.0;
@@ -1121,7 +1133,7 @@ static hipError_t sweep_rows_t(const MultiVI &V, int t_hi, double *wg_res, doubl
   if (e != hipSuccess) return e;
   const VIParams &P = V.d[0].P;
   const int win = P.win_rows * P.nx;
-  const size_t lds = ((size_t)kRowQ + 8 + (size_t)M * (win + P.states_per_wg)) * 8;
+  const size_t lds = ((size_t)kRowQ + 8 + (size_t)M * (win + 1 + P.states_per_wg)) * 8;
   const int64_t nb = (int64_t)t_hi * P.blocks_per_layer;
   const int grid = vi_grid(nb, kViGridMax);
   hipLaunchKernelGGL(k_vi_sweep_rows<M>, dim3(grid), dim3(kBlock), lds, s, V, t_hi, win, wg_res);
