@@ -44,13 +44,13 @@ HBM_BW = 8.0e12                        # bytes/s
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
     ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                               read=406577488, write=477810063, valu_insts=11608623532),
+                               read=406727477, write=477813514, valu_insts=11608623532),
     ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                                      read=377146816, write=888010416, valu_insts=11949287382),
-    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="75e7d4a4bd72925e",
-                                          read=3165550183, write=32609907, valu_insts=279657759),
-    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="75e7d4a4bd72925e",
-                                                 read=294775541, write=14990360, valu_insts=50547188),
+                                      read=377113216, write=888004496, valu_insts=11949287382),
+    ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="b9fad8aee23f57f8",
+                                          read=3165857864, write=32609971, valu_insts=279657759),
+    ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="b9fad8aee23f57f8",
+                                                 read=294719759, write=14990361, valu_insts=50547188),
 }
 
 

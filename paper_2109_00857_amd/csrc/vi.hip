@@ -892,12 +892,14 @@ __device__ inline void vi_block_rows(const MultiVI &V, int live, int odd, int t,
         for (int j = 0; j < kRowUnroll; ++j) x[j] = vw[min(ent[h][j] >> 16, wz)];
 #pragma unroll
         for (int j = 0; j < kRowUnroll; ++j) acc[h] += (double)(ent[h][j] & 0xFFFFu) * x[j];
-      } else {  // one at a time (several missions' registers: reading them together spills)
+      } else {  // two at a time (several missions' registers: reading more together spills)
 #pragma unroll
-        for (int j = 0; j < kRowUnroll; ++j) {
-          uint32_t e = ent[h][j];
-          asm volatile("" : "+v"(e));  // decoded per mission
-          acc[h] += (double)(e & 0xFFFFu) * vw[min(e >> 16, wz)];
+        for (int j = 0; j < kRowUnroll; j += 2) {
+          uint32_t e0 = ent[h][j], e1 = ent[h][j + 1];
+          asm volatile("" : "+v"(e0), "+v"(e1));  // decoded per mission
+          const double x0 = vw[min(e0 >> 16, wz)], x1 = vw[min(e1 >> 16, wz)];
+          acc[h] += (double)(e0 & 0xFFFFu) * x0;
+          acc[h] += (double)(e1 & 0xFFFFu) * x1;
         }
       }
       for (int k = kRowUnroll; k < len[h]; ++k) {  // the rest of a long row
