@@ -43,14 +43,14 @@ HBM_BW = 8.0e12                        # bytes/s
 # scaled to bytes by the plain-copy calibration (FETCH x2.000, WRITE x1.000);
 # valu_insts is SQ_INSTS_VALU (wave instructions) per launch.
 MEASURED = {
-    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                               read=406727477, write=477813514, valu_insts=11608623532),
-    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="7da640c6a95aa1ca",
-                                      read=377113216, write=888004496, valu_insts=11949287382),
+    ("k_build", "large"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="8467cb26c0ccf1b2",
+                               read=406806330, write=477817336, valu_insts=11386517926),
+    ("k_build", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/build.hip", sha256="8467cb26c0ccf1b2",
+                                      read=380743296, write=888004032, valu_insts=11858140138),
     ("k_vi_sweep_rows<1>", "large"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="b9fad8aee23f57f8",
-                                          read=3165857864, write=32609971, valu_insts=279657759),
+                                          read=3165340749, write=32609961, valu_insts=279657759),
     ("k_vi_sweep_rows<3>", "paper_shaped"): dict(src="paper_2109_00857_amd/csrc/vi.hip", sha256="b9fad8aee23f57f8",
-                                                 read=294719759, write=14990361, valu_insts=50547188),
+                                                 read=294722012, write=14990360, valu_insts=50547188),
 }
 
 

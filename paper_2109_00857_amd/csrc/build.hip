@@ -338,6 +338,19 @@ __device__ void build_tile(const PT &P, const int t, const int tile, BuildState 
           int g = g0;
           if (g < g1) {
             float4 A0 = st4[2 * g], A1 = st4[2 * g + 1];
+            for (; g + 4 < g1; g += 4) {  // four groups an iteration, two register sets
+              float4 B0 = st4[2 * g + 2], B1 = st4[2 * g + 3];
+              four(A0, A1);
+              A0 = st4[2 * g + 4];
+              A1 = st4[2 * g + 5];
+              four(B0, B1);
+              B0 = st4[2 * g + 6];
+              B1 = st4[2 * g + 7];
+              four(A0, A1);
+              A0 = st4[2 * g + 8];
+              A1 = st4[2 * g + 9];
+              four(B0, B1);
+            }
             for (; g + 2 < g1; g += 2) {
               const float4 B0 = st4[2 * g + 2], B1 = st4[2 * g + 3];
               four(A0, A1);
